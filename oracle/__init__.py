@@ -1,0 +1,291 @@
+"""FP64 CPU oracle for convolutional gridding, imaging and their adjoints.
+
+Test infrastructure only: only tests/, ``__graft_entry__.smoke()`` and the cpu_baseline leg
+of ``bench.py`` import it. It shares no code with the HIP library (``paper_0902_0915_amd``):
+its kernel comes from ``oracle.pswf`` (Legendre eigen-solution via numpy), its loops from
+``oracle/oracle.c`` (plain FP64 C, built with -ffp-contract=off), its FFTs from numpy.
+
+Each function cites the part of the paper it follows. The paper gives one sentence on the
+gridding step (Section 2.1), says the images come from a Fourier transform (Section 2,
+Section 2.1) and lists the steps Gridding, FFT and Convolution Correction with their timings
+(Table 1); every concrete rule below is a reading of that text, listed in the design doc.
+
+Array conventions (all numpy):
+  uvw      float64 [nrow, 3] metres          freq   float64 [nchan] Hz
+  vis      complex [nrow*nchan, npol]         flags  uint8/bool [nrow*nchan] or None
+  weights  float [nrow*nchan] or None         gains  complex [nant] or None, ant1/ant2 [nrow]
+  pos      int32 [ngroups, 4] = cx, cy, px, py (-1 where dropped), keep bool [ngroups]
+  grid     complex128 [npol, ny, nx]          image  complex128 [npol, ny, nx]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import pswf
+from .pswf import correction, kernel_table, psi0  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from .build import build
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_positions.argtypes = [_I64, _I32, _P, _P, _P, _P, _I32, _I32, _D, _D, _I32, _P, _I32,
+                                  _P, _P, _P]
+    lib.orc_grid.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32,
+                             _P, _P, _I32]
+    lib.orc_degrid.argtypes = lib.orc_grid.argtypes
+    lib.orc_grid_stack.argtypes = [_I64, _I32, _P, _P, _P, _P, _P, _P, _P, _I32, _I32, _I32,
+                                   _I32, _P, _P, _P, _P, _P, _I32]
+    lib.orc_degrid_stack.argtypes = lib.orc_grid_stack.argtypes
+    for f in (lib.orc_positions, lib.orc_grid, lib.orc_degrid, lib.orc_grid_stack,
+              lib.orc_degrid_stack):
+        f.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _threads(nthreads):
+    if nthreads is None or nthreads <= 0:
+        return max(1, len(os.sched_getaffinity(0)))
+    return int(nthreads)
+
+
+def _c(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _cplx(a):
+    """complex array -> contiguous float64 view [..., 2] (upcast to complex128 first)."""
+    if a is None:
+        return None
+    z = np.ascontiguousarray(a, dtype=np.complex128)
+    return z.view(np.float64)
+
+
+# ---------------------------------------------------------------------------------------------
+# Positions, quantisation, keep rule (Section 2.1 "interpolates the samples onto a regular grid")
+# ---------------------------------------------------------------------------------------------
+def positions(uvw, freq, nx, ny, du, dv, W, O, flags=None, weights=None, half=None):
+    """Quantised grid position of every (row, channel) group, and the keep mask.
+
+    u = (u_m * f)/c, x = u/du + nx/2, qx = floor(x*O + 1/2), cx = floor((qx + O/2)/O),
+    px = qx - cx*O (same in y). A group is dropped if it is flagged, has zero weight, or its
+    footprint [cx-h, cx+h] x [cy-h, cy+h] leaves the grid. ``half`` gives a per-group half
+    support (kernel stacks); otherwise h = (W-1)/2.
+
+    Returns (pos int32 [ngroups, 4], keep bool [ngroups], counts dict).
+    """
+    lib = _load()
+    uvw = _c(uvw, np.float64)
+    freq = _c(freq, np.float64)
+    nrow, nchan = uvw.shape[0], freq.shape[0]
+    ng = nrow * nchan
+    flags = _c(flags, np.uint8)
+    weights = _c(weights, np.float64)
+    half = _c(half, np.int32)
+    for a in (flags, weights, half):
+        if a is not None and a.size != ng:
+            raise ValueError("per-group array has the wrong length")
+    pos = np.empty((ng, 4), dtype=np.int32)
+    keep = np.empty(ng, dtype=np.uint8)
+    counts = np.zeros(3, dtype=np.int64)
+    lib.orc_positions(nrow, nchan, _ptr(uvw), _ptr(freq), _ptr(flags), _ptr(weights), nx, ny,
+                      float(du), float(dv), O, _ptr(half), (W - 1) // 2, _ptr(pos), _ptr(keep),
+                      _ptr(counts))
+    return pos, keep.astype(bool), {"kept": int(counts[0]), "flagged": int(counts[1]),
+                                    "outside": int(counts[2])}
+
+
+def _gain_args(gains, ant1, ant2):
+    if gains is None:
+        return None, None, None
+    if ant1 is None or ant2 is None:
+        raise ValueError("gains need ant1 and ant2")
+    return _cplx(gains), _c(ant1, np.int32), _c(ant2, np.int32)
+
+
+# ---------------------------------------------------------------------------------------------
+# Gridding (Section 2.1; Table 1 "Gridding")
+# ---------------------------------------------------------------------------------------------
+def grid(pos, keep, vis, nx, ny, W, O, nchan=1, weights=None, gains=None, ant1=None, ant2=None,
+         table=None, out=None, nthreads=None):
+    """G[pol][cy+s][cx+t] += w * g1 * conj(g2) * T[py][s] * T[px][t] * V[pol] (complex128)."""
+    lib = _load()
+    vis2 = np.asarray(vis)
+    if vis2.ndim == 1:
+        vis2 = vis2[:, None]
+    ng, npol = vis2.shape
+    if npol > 16:
+        raise ValueError("npol > 16")
+    if table is None:
+        table = kernel_table(W, O)
+    table = _c(table, np.float64)
+    pos = _c(pos, np.int32)
+    keep8 = _c(keep, np.uint8)
+    visd = _cplx(vis2)
+    g, a1, a2 = _gain_args(gains, ant1, ant2)
+    w = _c(weights, np.float64)
+    if out is None:
+        out = np.zeros((npol, ny, nx), dtype=np.complex128)
+    assert out.dtype == np.complex128 and out.flags.c_contiguous
+    lib.orc_grid(ng, npol, _ptr(pos), _ptr(keep8), _ptr(visd), _ptr(w), _ptr(g), _ptr(a1),
+                 _ptr(a2), int(nchan), nx, ny, W, O, _ptr(table), _ptr(out.view(np.float64)),
+                 _threads(nthreads))
+    return out
+
+
+def degrid(pos, keep, grid_, W, O, nchan=1, weights=None, gains=None, ant1=None, ant2=None,
+           table=None, nthreads=None):
+    """Adjoint of ``grid``: y[pol] = w * conj(g1) * g2 * sum_{s,t} T[py][s] T[px][t] G[...]."""
+    lib = _load()
+    npol, ny, nx = grid_.shape
+    if table is None:
+        table = kernel_table(W, O)
+    table = _c(table, np.float64)
+    pos = _c(pos, np.int32)
+    keep8 = _c(keep, np.uint8)
+    ng = pos.shape[0]
+    gd = _cplx(grid_)
+    g, a1, a2 = _gain_args(gains, ant1, ant2)
+    w = _c(weights, np.float64)
+    out = np.zeros((ng, npol), dtype=np.complex128)
+    lib.orc_degrid(ng, npol, _ptr(pos), _ptr(keep8), _ptr(gd), _ptr(w), _ptr(g), _ptr(a1),
+                   _ptr(a2), int(nchan), nx, ny, W, O, _ptr(table), _ptr(out.view(np.float64)),
+                   _threads(nthreads))
+    return out
+
+
+def grid_stack(pos, keep, vis, nx, ny, O, kstack, koffset, ksupport, kidx, nchan=1,
+               weights=None, gains=None, ant1=None, ant2=None, out=None, nthreads=None):
+    """Kernel-stack gridding: complex tap K_k[py][px][s][t] of the group's kernel k."""
+    lib = _load()
+    vis2 = np.asarray(vis)
+    if vis2.ndim == 1:
+        vis2 = vis2[:, None]
+    ng, npol = vis2.shape
+    if npol > 16:
+        raise ValueError("npol > 16")
+    ks = _cplx(kstack)
+    ko = _c(koffset, np.int64)
+    ksup = _c(ksupport, np.int32)
+    ki = _c(kidx, np.int32)
+    g, a1, a2 = _gain_args(gains, ant1, ant2)
+    w = _c(weights, np.float64)
+    if out is None:
+        out = np.zeros((npol, ny, nx), dtype=np.complex128)
+    lib.orc_grid_stack(ng, npol, _ptr(_c(pos, np.int32)), _ptr(_c(keep, np.uint8)),
+                       _ptr(_cplx(vis2)), _ptr(w), _ptr(g), _ptr(a1), _ptr(a2), int(nchan), nx,
+                       ny, O, _ptr(ks), _ptr(ko), _ptr(ksup), _ptr(ki),
+                       _ptr(out.view(np.float64)), _threads(nthreads))
+    return out
+
+
+def degrid_stack(pos, keep, grid_, O, kstack, koffset, ksupport, kidx, nchan=1, weights=None,
+                 gains=None, ant1=None, ant2=None, nthreads=None):
+    """Adjoint of ``grid_stack`` (conjugated taps)."""
+    lib = _load()
+    npol, ny, nx = grid_.shape
+    pos = _c(pos, np.int32)
+    ng = pos.shape[0]
+    g, a1, a2 = _gain_args(gains, ant1, ant2)
+    w = _c(weights, np.float64)
+    out = np.zeros((ng, npol), dtype=np.complex128)
+    lib.orc_degrid_stack(ng, npol, _ptr(pos), _ptr(_c(keep, np.uint8)), _ptr(_cplx(grid_)),
+                         _ptr(w), _ptr(g), _ptr(a1), _ptr(a2), int(nchan), nx, ny, O,
+                         _ptr(_cplx(kstack)), _ptr(_c(koffset, np.int64)),
+                         _ptr(_c(ksupport, np.int32)), _ptr(_c(kidx, np.int32)),
+                         _ptr(out.view(np.float64)), _threads(nthreads))
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Image = FFT, and convolution correction (Section 2, Section 2.1; Table 1 "FFT",
+# "Convolution Correction")
+# ---------------------------------------------------------------------------------------------
+def _corr2d(ny, nx, W):
+    return correction(ny, W)[:, None] * correction(nx, W)[None, :]
+
+
+def image(grid_, W=7, correct=True):
+    """Centred, unnormalised 2-D transform with sign +i, per polarisation:
+
+        I[p] = sum_g G[g] exp(+2 pi i (g - N/2)(p - N/2)/N)   (separately in x and y)
+
+    then, if ``correct``, division by the normalised kernel transform at each pixel.
+    """
+    g = np.asarray(grid_, dtype=np.complex128)
+    ny, nx = g.shape[-2:]
+    img = (nx * ny) * np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(g, axes=(-2, -1)),
+                                                   axes=(-2, -1)), axes=(-2, -1))
+    if correct:
+        img = img / _corr2d(ny, nx, W)
+    return img
+
+
+def image_adjoint(img, W=7, correct=True):
+    """Exact adjoint of ``image``: the correction first, then the sign -i unnormalised FFT."""
+    z = np.asarray(img, dtype=np.complex128)
+    ny, nx = z.shape[-2:]
+    if correct:
+        z = z / _corr2d(ny, nx, W)
+    return np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(z, axes=(-2, -1)), axes=(-2, -1)),
+                           axes=(-2, -1))
+
+
+# ---------------------------------------------------------------------------------------------
+# Differentiable imaging: loss and gradients in torch's convention (dL/dRe + i dL/dIm).
+# Calibration solves for per-antenna complex gains (Section 2); here the gains enter the
+# forward model g1 * conj(g2) * V and the gradients flow back through the adjoints.
+# ---------------------------------------------------------------------------------------------
+def loss_and_grads(pos, keep, vis, gains, ant1, ant2, target, nx, ny, W, O, nchan=1,
+                   weights=None, correct=True, nthreads=None):
+    """L = sum |image(grid(g1 conj(g2) V)) - target|^2, with dL/dV and dL/dg.
+
+    grad_I = 2 (I - target); grad_G = image_adjoint(grad_I); gamma = degrid(grad_G) without
+    gains; grad_V = conj(g1) g2 gamma;
+    grad_g[a] = sum_{a1 = a} g2 conj(V) gamma + sum_{a2 = a} g1 V conj(gamma) (summed over pols).
+    """
+    vis2 = np.asarray(vis, dtype=np.complex128)
+    if vis2.ndim == 1:
+        vis2 = vis2[:, None]
+    gains = np.asarray(gains, dtype=np.complex128)
+    ant1 = np.asarray(ant1, dtype=np.int64)
+    ant2 = np.asarray(ant2, dtype=np.int64)
+    G = grid(pos, keep, vis2, nx, ny, W, O, nchan=nchan, weights=weights, gains=gains,
+             ant1=ant1, ant2=ant2, nthreads=nthreads)
+    img = image(G, W=W, correct=correct)
+    diff = img - target
+    loss = float(np.sum(np.abs(diff) ** 2))
+    grad_img = 2.0 * diff
+    grad_grid = image_adjoint(grad_img, W=W, correct=correct)
+    gamma = degrid(pos, keep, grad_grid, W, O, nchan=nchan, weights=weights, nthreads=nthreads)
+    rows = np.arange(vis2.shape[0]) // nchan
+    g1 = gains[ant1[rows]][:, None]
+    g2 = gains[ant2[rows]][:, None]
+    grad_vis = np.conj(g1) * g2 * gamma
+    term1 = np.sum(g2 * np.conj(vis2) * gamma, axis=1)
+    term2 = np.sum(g1 * vis2 * np.conj(gamma), axis=1)
+    grad_g = np.zeros(gains.shape[0], dtype=np.complex128)
+    np.add.at(grad_g, ant1[rows], term1)
+    np.add.at(grad_g, ant2[rows], term2)
+    return loss, img, grad_vis, grad_g
