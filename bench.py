@@ -1,0 +1,211 @@
+"""Benchmark of the gridding + imaging hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (synthetic, seeded): the MWA-scale configuration - 512 antennas (density ~ 1/r
+within 1.5 km), 130,816 baselines x 32 channels x 8 times x 4 polarisations =
+133,955,584 complex64 visibilities from 1000 power-law point sources; 2048^2 grid per
+polarisation; prolate kernel support 7, oversampling 8; FP32 accumulation.
+
+A step is one forward pass of the imaging hot path over the batch, with the plan (FP64
+positions, tile sort, work list, kernel tables) built once beforehand for these uvw:
+mw_grid (zeroing included) then mw_image (+1, with the convolution correction). The plan,
+the gridder kernel alone, and a forward+backward pass (adding the image adjoint and the
+degridder) are reported beside it. Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mvis/s gridded (support 7, 2048² grid) + % HBM roofline; fwd+bwd vs plain"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed); see the design doc
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000,
+                    help="visibility groups (of 4 pols) in the oracle's timed sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--wg-waves", type=int, default=0)
+    ap.add_argument("--flush", type=int, default=0)
+    ap.add_argument("--order", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0)
+    return ap.parse_args()
+
+
+def timed(fn, steps, stream):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall * 1e3 / steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        n = 1 << 28  # 2^28 floats = 1 GiB
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 3}))
+        return
+
+    from paper_0902_0915_amd import mwagrid, synth
+
+    t0 = time.perf_counter()
+    log("generating the MWA-scale workload (uvw, 1000-source sky, visibilities on device)")
+    wl = synth.mwa_scale(device="cuda")
+    vis = wl.vis
+    torch.cuda.synchronize()
+    log(f"generated {wl.ngroups} groups x {wl.npol} pols in {time.perf_counter() - t0:.1f} s")
+
+    tuning = {k: v for k, v in dict(tile=args.tile, split=args.split, wg_waves=args.wg_waves,
+                                     flush=args.flush, order=args.order,
+                                     variant=args.variant).items() if v}
+    spec = mwagrid.InstanceSpec.from_workload(wl, with_ants=False)
+    t0 = time.perf_counter()
+    plan = mwagrid.Plan(spec, tuning=tuning or None)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    info = plan.info(0)
+    log(f"plan built in {plan_ms:.1f} ms: {info}")
+
+    grid = torch.empty((wl.npol, wl.ny, wl.nx), dtype=torch.complex64, device="cuda")
+    img = torch.empty_like(grid)
+    gback = torch.empty_like(grid)
+    vout = torch.empty_like(vis)
+
+    def step():
+        plan.grid(vis, out=grid)
+        plan.image(grid, direction=1, correct=True, out=img)
+
+    def grid_kernel_only():
+        plan.grid(vis, out=grid, accumulate=True)  # the gridder launch alone (no zeroing)
+
+    def fwd_bwd():
+        plan.grid(vis, out=grid)
+        plan.image(grid, direction=1, correct=True, out=img)
+        plan.image(img, direction=-1, correct=True, out=gback)
+        plan.degrid(gback, out=vout)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
+    ev_ms, wall_ms = timed(step, args.steps, stream)
+    log(f"step: {ev_ms:.3f} ms (events), {wall_ms:.3f} ms (wall)")
+    kern_ms, _ = timed(grid_kernel_only, args.steps, stream)
+    log(f"gridder kernel alone: {kern_ms:.3f} ms")
+    fb_ms, _ = timed(fwd_bwd, max(1, args.steps // 2), stream)
+    log(f"forward + backward: {fb_ms:.3f} ms")
+
+    nvis = info["nkept"] * wl.npol
+    value = nvis / (wall_ms * 1e-3) / 1e6
+    # Gridder algorithmic traffic: every kept visibility read once (8 B per pol) and the
+    # grid written once (8 B per cell per pol); flops: 49 taps x npol x complex FMA (4 flop).
+    alg_bytes = info["nkept"] * wl.npol * 8 + wl.npol * wl.nx * wl.ny * 8
+    alg_flop = info["nkept"] * wl.W * wl.W * wl.npol * 4
+    hbm_gbs = alg_bytes / (kern_ms * 1e-3) / 1e9
+    tflops = alg_flop / (kern_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "kernel": "k_grid_taplanes<4>",
+                "kernel_ms": round(kern_ms, 4), "alg_flop": alg_flop}
+    hbm = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "alg_bytes": alg_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, vis, args.cpu_sample)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mvis/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "mwa_scale: 512 antennas (1/r density, 1.5 km), 130816 baselines"
+                               " x 32 channels x 8 times x 4 pols, 1000 sources, 2048^2 grid,"
+                               " W=7, O=8", "visibilities": nvis, "grid": [wl.npol, wl.ny, wl.nx],
+                   "launch": {k: info[k] for k in ("tile", "split", "wg_waves", "order",
+                                                   "variant", "flush", "nwork")}},
+        "roofline": roofline,
+        "hbm_roofline": hbm,
+        "grid_only_mvis_s": round(nvis / (kern_ms * 1e-3) / 1e6, 1),
+        "step_event_ms": round(ev_ms, 4),
+        "plan_ms": round(plan_ms, 1),
+        "fwd_bwd_ms": round(fb_ms, 4),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def cpu_baseline(wl, vis_dev, sample_groups):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload: positions,
+    gridding of the first ``sample_groups`` groups (all host cores, row stripes) and the
+    image with correction; scaled to Mvis/s."""
+    import numpy as np
+
+    import oracle as orc
+
+    ng = min(sample_groups, wl.ngroups)
+    nrow = ng // wl.nchan
+    ng = nrow * wl.nchan
+    cores = len(os.sched_getaffinity(0))
+    log(f"cpu baseline: oracle on {ng} groups ({nrow} rows) with {cores} threads")
+    vis = vis_dev[:ng].cpu().numpy()
+    t0 = time.perf_counter()
+    pos, keep, _ = orc.positions(wl.uvw[:nrow], wl.freq, wl.nx, wl.ny, wl.du, wl.dv, wl.W, wl.O)
+    G = orc.grid(pos, keep, vis, wl.nx, wl.ny, wl.W, wl.O, nchan=wl.nchan, nthreads=cores)
+    orc.image(G, W=wl.W, correct=True)
+    dt = time.perf_counter() - t0
+    nv = int(keep.sum()) * wl.npol
+    log(f"cpu baseline: {dt:.2f} s")
+    return {"value": round(nv / dt / 1e6, 3), "unit": "Mvis/s", "cores": cores,
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"first {nrow} rows x {wl.nchan} channels x {wl.npol} pols of the same "
+                      f"workload ({nv} visibilities), positions + grid + corrected image"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * mwagrid.h - C ABI of libmwagrid, convolutional gridding of radio visibilities onto the
+ * uv-plane, the FFT to per-polarisation images with kernel correction, and the exact
+ * adjoints of both, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the paper's statement of the imaging step: the calibrated
+ * visibilities, samples of the Fourier transform of the sky (Section 2.1), are convolved so
+ * that they are interpolated onto a regular grid on which an FFT can operate (Section 2.1);
+ * the FFT turns the grid into images, one per instrumental polarisation (Section 2,
+ * Section 2.1), which are then convolution-corrected (Table 1: Gridding, FFT, Convolution
+ * Correction). The paper fixes no kernel, grid convention or precision; the rules used here
+ * are stated at each call.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A "group" is one (row, channel) pair; a row is one baseline at one time. Group g =
+ *    row * nchan + chan. Visibilities are complex64 (float re, float im) laid out
+ *    [ngroups][npol], contiguous.
+ *  - A grid or image is complex64 [npol][ny][nx], contiguous (x fastest). Column x holds
+ *    u = (x - nx/2) * du, row y holds v = (y - ny/2) * dv.
+ *  - Positions (computed once, in FP64, at plan time): u = (u_m * f) / 299792458,
+ *    x = u/du + nx/2, qx = floor(x*O + 1/2), cx = floor((qx + O/2)/O), px = qx - cx*O; the
+ *    same for y. A group is dropped (never gridded, adjoint output zero) if it is flagged, its
+ *    weight is zero, its position is not finite, or its footprint [cx-h, cx+h] x [cy-h, cy+h]
+ *    leaves the grid (h = (W-1)/2, or the half support of its kernel for stacks).
+ *  - Built-in kernel: the zeroth prolate spheroidal wave function C(t) = psi_0(c, 2t/W),
+ *    c = pi*W/2, tabulated at O phases; each phase row is normalised to unit sum. Tap of
+ *    group g at cell (cx+t, cy+s) is T[py][s] * T[px][t].
+ *  - Device pointers passed to grid/degrid/image must be on the device that was current when
+ *    the plan was made; "stream" is a hipStream_t (NULL = the null stream). Those calls only
+ *    enqueue work; kernel faults surface at the caller's next synchronisation.
+ *  - Every call returns an mw_status; on failure mw_last_error() describes it. No call
+ *    aborts, prints or throws across this boundary. A plan serves one stream at a time;
+ *    concurrent calls on one plan from several threads are not supported.
+ */
+#ifndef MWAGRID_H
+#define MWAGRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MW_ABI_VERSION 1
+
+typedef enum {
+    MW_OK = 0,
+    MW_ERR_INVALID_ARG = 1, /* a null pointer, size or option outside its documented range */
+    MW_ERR_UNSUPPORTED = 2, /* valid in principle but beyond this build's limits */
+    MW_ERR_ALLOC = 3,       /* device or pinned host allocation failed */
+    MW_ERR_HIP = 4,         /* a HIP runtime or rocFFT call failed */
+    MW_ERR_STATE = 5        /* the plan cannot serve this call (e.g. destroyed, wrong form) */
+} mw_status;
+
+enum { MW_MEM_HOST = 0, MW_MEM_DEVICE = 1 };
+
+typedef struct mw_plan_s *mw_plan; /* opaque; owned by the library until mw_plan_destroy */
+
+/*
+ * One gridding instance: one grid, the visibilities' coordinates and how to weight them.
+ * Arrays are read during mw_grid_plan only (host or device memory as "mem" says); the plan
+ * keeps its own copies of everything it needs afterwards.
+ */
+typedef struct {
+    int32_t nx, ny;               /* grid size; even, 8 <= n <= 4096 */
+    double du, dv;                /* cell size in wavelengths, > 0 */
+    int64_t nrow;                 /* rows (baseline-times); ngroups = nrow * nchan < 2^31 */
+    int32_t nchan;                /* channels, >= 1 */
+    int32_t npol;                 /* polarisations per group: 1, 2 or 4 */
+    const double *uvw_m;          /* [nrow][3] baseline coordinates in metres (w unused) */
+    const double *freq_hz;        /* [nchan] channel frequencies */
+    const uint8_t *flags;         /* [ngroups] nonzero = flagged; NULL = none */
+    const float *weights;         /* [ngroups] real weights; NULL = all 1 */
+    const int32_t *ant1, *ant2;   /* [nrow] antenna indices in [0, nant); NULL = no gains */
+    int32_t nant;                 /* antennas (when ant1/ant2 are given), <= 65535 */
+    int32_t support;              /* W: odd, 1 <= W <= 15 (built-in kernel; 0 with stacks) */
+    int32_t oversample;           /* O: 1 <= O <= 16 */
+    /* Kernel stacks (NULL kernel_stack = built-in kernel). Kernel k has odd support
+     * S = kernel_support[k] (1 <= S <= 63) and complex64 taps at element
+     * kernel_offset[k] of kernel_stack laid out [O][O][S][S]: phase row py + O/2, phase
+     * column px + O/2, tap row s + h, tap column t + h. kernel_index[g] selects the kernel
+     * of group g. The adjoint uses conjugated taps. */
+    const void *kernel_stack;
+    const int64_t *kernel_offset; /* [nkernel] */
+    const int32_t *kernel_support;/* [nkernel] */
+    int32_t nkernel;
+    int64_t kernel_elems;         /* complex elements in kernel_stack */
+    const int32_t *kernel_index;  /* [ngroups] */
+    int32_t mem;                  /* MW_MEM_HOST or MW_MEM_DEVICE for all arrays above */
+} mw_instance;
+
+/* Optional launch choices. Zero fields mean "choose automatically". */
+typedef struct {
+    int32_t tile;       /* uv tile edge in cells: 16, 32 or 64 */
+    int32_t split;      /* max groups per work item (heavy tiles are split), >= 64 */
+    int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 */
+    int32_t order;      /* 1 = groups sorted by cell within a tile, 2 = input order */
+    int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes (npol 4), 3 = scatter */
+    int32_t flush;      /* 1 = atomic tile flush, 2 = deterministic two-pass merge */
+    int32_t autotune;   /* 1 = time candidate launches on this plan's data and keep the best */
+} mw_tuning;
+
+typedef struct {
+    int64_t ngroups, nkept, nflagged, noutside;
+    int32_t ntiles, nwork;        /* non-empty tiles and work items */
+    int32_t tile, split, wg_waves, order, variant, flush; /* the launch actually chosen */
+    int64_t plan_bytes;           /* device memory owned by the plan for this instance */
+} mw_plan_stats;
+
+/*
+ * Build a plan for ninst instances (ninst >= 1). Computes every group's position in FP64
+ * (the quantisation rule above), drops flagged and out-of-grid groups, sorts the kept ones
+ * by uv tile (and cell), splits heavy tiles into work items, builds the kernel table and
+ * correction vectors, and (ninst > 1) the persistent batched schedule. Synchronous: returns
+ * after all work on "stream" is done. tuning may be NULL. On success *out owns device memory
+ * until mw_plan_destroy.
+ * Errors: MW_ERR_INVALID_ARG (null out/inst, a field out of range), MW_ERR_UNSUPPORTED
+ * (limits above), MW_ERR_ALLOC, MW_ERR_HIP.
+ */
+mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst,
+                       const mw_tuning *tuning, void *stream);
+
+/*
+ * Grid: for every instance i, grid[i] (+)= sum over kept groups of
+ *   w * g[ant1] * conj(g[ant2]) * tap * V[pol]   (separable or stack tap, see above).
+ * vis[i]: device complex64 [ngroups][npol]. gains: NULL, or gains[i] NULL or device
+ * complex64 [nant]. grid[i]: device complex64 [npol][ny][nx]. accumulate = 0 overwrites the
+ * grid (zeroing is part of the call); 1 adds to it. FP32 accumulation; the summation order
+ * is not fixed unless the deterministic flush was chosen.
+ * Errors: MW_ERR_INVALID_ARG (null plan/arrays), MW_ERR_STATE (gains for an instance planned
+ * without antennas), MW_ERR_HIP (launch failure).
+ */
+mw_status mw_grid(mw_plan plan, const void *const *vis, const void *const *gains,
+                  void *const *grid, int32_t accumulate, void *stream);
+
+/*
+ * Degrid, the exact adjoint of mw_grid: for every instance and kept group,
+ *   vis_out[g][pol] = w * conj(g[ant1]) * g[ant2] * sum_taps conj?(tap) * grid[pol][cell]
+ * (conjugated taps for stacks), and 0 for dropped groups. vis_out is overwritten.
+ * If grad_gains[i] is non-NULL it receives (overwritten, complex64 [nant]) the gradient of a
+ * real loss with respect to the gains of the forward model w * g1 * conj(g2) * V, given that
+ * grid[i] holds the gradient with respect to the grid (torch convention dL/dRe + i dL/dIm):
+ *   grad_g[a] = sum_{ant1 = a} g2 conj(V) y + sum_{ant2 = a} g1 V conj(y),
+ * with y the adjoint output without gains and V = vis_in[i] (required then).
+ * Errors: MW_ERR_INVALID_ARG, MW_ERR_STATE (gains for an instance without antennas),
+ * MW_ERR_HIP.
+ */
+mw_status mw_degrid(mw_plan plan, const void *const *grid, const void *const *gains,
+                    const void *const *vis_in, void *const *vis_out, void *const *grad_gains,
+                    void *stream);
+
+/*
+ * Image, per instance and polarisation. direction = +1:
+ *   out[p] = sum_g in[g] exp(+2 pi i (g - n/2)(p - n/2)/n) in x and y (unnormalised,
+ *   centred), then, if correct, out /= Cn(x) Cn(y) with Cn(x) = psi_0(c, 2x)/psi_0(c, 0),
+ *   x = (p - n/2)/n (the normalised Fourier transform of the built-in kernel).
+ * direction = -1 is the exact adjoint: the correction first, then the sign -i transform.
+ * in and out are device complex64 [npol][ny][nx]; in == out is allowed (in place); in is
+ * left unchanged otherwise. correct = 1 is rejected for instances planned with stacks.
+ * Errors: MW_ERR_INVALID_ARG, MW_ERR_STATE, MW_ERR_HIP.
+ */
+mw_status mw_image(mw_plan plan, const void *const *in, void *const *out, int32_t direction,
+                   int32_t correct, void *stream);
+
+/* Statistics and chosen launch of instance inst (inst = -1: sums over instances). */
+mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out);
+
+/*
+ * Copy instance inst's integer plan outputs to host memory: pos_host int32 [ngroups][4] =
+ * cx, cy, px, py for kept groups and -1, -1, -1, -1 for dropped ones. Synchronous.
+ */
+mw_status mw_plan_positions(mw_plan plan, int32_t inst, int32_t *pos_host);
+
+/*
+ * Copy instance inst's kernel tables to host memory (built-in kernel only; any pointer may
+ * be NULL): table_host float [O][W] (row = phase + O/2), corr_x float [nx], corr_y [ny].
+ */
+mw_status mw_plan_tables(mw_plan plan, int32_t inst, float *table_host, float *corr_x,
+                         float *corr_y);
+
+/* Release everything the plan owns (waits for its outstanding work). NULL is a no-op. */
+mw_status mw_plan_destroy(mw_plan plan);
+
+/* Description of the last failure on the calling thread; valid until its next call. */
+const char *mw_last_error(void);
+
+/* MW_ABI_VERSION of the library. */
+int32_t mw_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MWAGRID_H */

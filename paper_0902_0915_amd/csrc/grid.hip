@@ -1,0 +1,407 @@
+// Gridding kernels: scatter every kept visibility through its W x W kernel footprint onto
+// the uv grid (the interpolation onto a regular grid of Section 2.1; "Gridding" in Table 1).
+//
+// The paper's port replaced scatter loops by gather loops because its GPU had no atomic
+// floating-point add (Section 3.2). CDNA4 has fast LDS FP32 atomics, so this gridder keeps
+// the scatter but confines it to the chip: visibilities arrive sorted by uv tile (plan
+// time), one workgroup owns one tile (or one slice of a heavy tile) staged in LDS with a
+// halo of h cells, and only the finished tile goes to HBM, with coalesced stores.
+//
+// Variant 1 ("tap lanes", W*W <= 64): lane l of a wavefront owns tap (s, t) = (l / W, l % W)
+// of the footprint and holds one FP32 accumulator per polarisation component in registers.
+// Groups are sorted by cell within the tile, so consecutive groups often share a centre
+// cell; the accumulators are only added into the LDS tile when the (wave-uniform) centre
+// cell changes. Each group costs one tap read from LDS and 2*npol FMAs per lane.
+//
+// Variant 3 ("scatter", any W <= 15): one thread per group adds all W*W taps into the LDS
+// tile with LDS atomics.
+//
+// Tile flush: 1 = atomic adds of the tile (with halo) into the zeroed grid in HBM;
+//             2 = plain stores of each tile into a per-work-item buffer and a merge pass
+//                 that sums the (at most nine) overlapping tiles of every cell.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace mwg {
+
+size_t taplanes_lds(int npol, int T, int W, int O, int waves);
+size_t scatter_lds(int npol, int T, int W, int O);
+
+namespace {
+
+constexpr int kFillBlock = 256;
+
+__global__ void k_fill_zero4(float4 *p, int64_t n4) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < n4; k += stride) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_fill_zero1(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+struct GridArgs {
+    const float2 *vis;
+    const uint32_t *perm, *spos, *sant;
+    const float *sw;
+    const float2 *gains;
+    const WorkItem *work;
+    const float *taps2d, *tab;
+    float2 *grid;
+    float *partial;  // flush 2
+    int nx, ny, T, ntx, W, O, str, plane;
+};
+
+// LDS layout of a tile: 2*NPOL planes (re, im of each polarisation), each R rows of STR
+// floats, R = T + W - 1; STR = W (mod 32) makes the 49 lanes of a footprint flush hit 49
+// distinct banks. The plane size is padded to a multiple of 4 floats.
+__host__ __device__ inline int tile_stride(int R, int W) {
+    int s = R;
+    while ((s - W) % 32 != 0) s++;
+    return s;
+}
+__host__ __device__ inline int tile_plane(int R, int STR) { return (R * STR + 3) & ~3; }
+
+// Multiply a group's visibilities by w * g1 * conj(g2) (when given).
+template <int NPOL>
+__device__ inline void apply_multiplier(const GridArgs &a, int64_t i, float2 (&v)[NPOL]) {
+    if (!a.sw && !a.gains) return;
+    float mr = a.sw ? a.sw[i] : 1.0f, mi = 0.0f;
+    if (a.gains) {
+        const uint32_t an = a.sant[i];
+        const float2 g1 = a.gains[an & 0xFFFFu], g2 = a.gains[an >> 16];
+        const float gr = g1.x * g2.x + g1.y * g2.y, gi = g1.y * g2.x - g1.x * g2.y;
+        mi = mr * gi;
+        mr = mr * gr;
+    }
+#pragma unroll
+    for (int p = 0; p < NPOL; p++) {
+        const float re = mr * v[p].x - mi * v[p].y, im = mr * v[p].y + mi * v[p].x;
+        v[p] = make_float2(re, im);
+    }
+}
+
+template <int NPOL>
+__device__ inline void load_vis(const float2 *vis, uint32_t g, float2 (&v)[NPOL]) {
+    const float2 *src = vis + (int64_t)g * NPOL;
+    if constexpr (NPOL == 4) {
+        const float4 a = ((const float4 *)src)[0], b = ((const float4 *)src)[1];
+        v[0] = make_float2(a.x, a.y);
+        v[1] = make_float2(a.z, a.w);
+        v[2] = make_float2(b.x, b.y);
+        v[3] = make_float2(b.z, b.w);
+    } else if constexpr (NPOL == 2) {
+        const float4 a = ((const float4 *)src)[0];
+        v[0] = make_float2(a.x, a.y);
+        v[1] = make_float2(a.z, a.w);
+    } else {
+        v[0] = src[0];
+    }
+}
+
+// Write the finished LDS tile to HBM (atomic adds, or plain stores into the work item's
+// slice of the partial buffer).
+template <int NPOL>
+__device__ inline void flush_tile(const GridArgs &a, const float *tile, int flush, int tx0, int ty0,
+                                  int h, int R, int STR, int PL) {
+    const int nthreads = blockDim.x;
+    if (flush == 1) {
+        for (int idx = threadIdx.x; idx < R * R; idx += nthreads) {
+            const int r = idx / R, c = idx - r * R;
+            const int gy = ty0 - h + r, gx = tx0 - h + c;
+            if (gy < 0 || gy >= a.ny || gx < 0 || gx >= a.nx) continue;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                const float re = tile[(2 * p) * PL + r * STR + c];
+                const float im = tile[(2 * p + 1) * PL + r * STR + c];
+                float *dst = (float *)(a.grid + ((int64_t)p * a.ny + gy) * a.nx + gx);
+                if (re != 0.0f) atomicAdd(dst, re);
+                if (im != 0.0f) atomicAdd(dst + 1, im);
+            }
+        }
+    } else {
+        float *out = a.partial + (int64_t)blockIdx.x * (2 * NPOL) * R * R;
+        for (int idx = threadIdx.x; idx < R * R; idx += nthreads) {
+            const int r = idx / R, c = idx - r * R;
+#pragma unroll
+            for (int q = 0; q < 2 * NPOL; q++) out[(int64_t)q * R * R + idx] = tile[q * PL + r * STR + c];
+        }
+    }
+}
+
+// Loads lane's group (index i of the sorted order) and applies its multiplier.
+template <int NPOL>
+__device__ inline void fetch_group(const GridArgs &a, int64_t i, uint32_t g, float2 (&v)[NPOL]) {
+    load_vis<NPOL>(a.vis, g, v);
+    apply_multiplier<NPOL>(a, i, v);
+}
+
+template <int NPOL>
+__global__ __launch_bounds__(1024) void k_grid_taplanes(GridArgs a, int flush) {
+    extern __shared__ __align__(16) float smem[];
+    const int nthreads = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = nthreads >> 6;
+    const WorkItem wk = a.work[blockIdx.x];
+    const int T = a.T, W = a.W, h = (W - 1) / 2, R = T + W - 1, STR = a.str, PL = a.plane;
+    const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
+    const int OO64 = a.O * a.O * 64;
+    float *tile = smem;
+    float *taps = smem + 2 * NPOL * PL;
+    float2 *sv = (float2 *)(taps + OO64) + wave * 64 * NPOL;
+
+    for (int i = tid; i < 2 * NPOL * PL; i += nthreads) tile[i] = 0.0f;
+    for (int i = tid; i < OO64; i += nthreads) taps[i] = a.taps2d[i];
+    __syncthreads();
+
+    const int n = wk.end - wk.begin;
+    const int wb = wk.begin + (int)((int64_t)n * wave / nwaves);
+    const int we = wk.begin + (int)((int64_t)n * (wave + 1) / nwaves);
+    const int s = lane / W, t = lane - s * W;
+    const bool active = lane < W * W;
+    const int loff = active ? s * STR + t : 0;
+    const float *tapl = taps + lane;
+    float acc[2 * NPOL];
+#pragma unroll
+    for (int k = 0; k < 2 * NPOL; k++) acc[k] = 0.0f;
+    int cur = -1;
+
+    // Software pipeline over batches of 64 groups: while batch k is accumulated from LDS,
+    // the visibilities of batch k+1 and the permutation entries of batch k+2 are in flight.
+    uint32_t gA = (wb + lane < we) ? a.perm[wb + lane] : 0u;
+    uint32_t gB = (wb + 64 + lane < we) ? a.perm[wb + 64 + lane] : 0u;
+    float2 vn[NPOL];
+    if (wb + lane < we) fetch_group<NPOL>(a, wb + lane, gA, vn);
+
+    for (int base = wb; base < we; base += 64) {
+        const int cnt = (we - base) < 64 ? (we - base) : 64;
+        if (lane < cnt) {
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) sv[lane * NPOL + p] = vn[p];
+        }
+        if (base + 64 + lane < we) fetch_group<NPOL>(a, base + 64 + lane, gB, vn);
+        gB = (base + 128 + lane < we) ? a.perm[base + 128 + lane] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t *spb = a.spos + base;
+        for (int j0 = 0; j0 < cnt; j0 += 8) {
+            uint32_t pp[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) pp[u] = spb[j0 + u]; // uniform; array padded by 64
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (j0 + u < cnt) {
+                    const uint32_t q = pp[u];
+                    const int cx = (int)(q & 0xFFFu), cy = (int)((q >> 12) & 0xFFFu);
+                    const int ph = (int)((q >> 28) * a.O + ((q >> 24) & 0xFu));
+                    const int cell = (cy - ty0) * STR + (cx - tx0);
+                    if (cell != cur) {
+                        if (cur >= 0 && active) {
+#pragma unroll
+                            for (int k = 0; k < 2 * NPOL; k++) atomicAdd(&tile[k * PL + cur + loff], acc[k]);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 2 * NPOL; k++) acc[k] = 0.0f;
+                        cur = cell;
+                    }
+                    const float tap = tapl[ph * 64];
+                    const float2 *vj = sv + (j0 + u) * NPOL;
+#pragma unroll
+                    for (int p = 0; p < NPOL; p++) {
+                        const float2 v = vj[p];
+                        acc[2 * p] = fmaf(tap, v.x, acc[2 * p]);
+                        acc[2 * p + 1] = fmaf(tap, v.y, acc[2 * p + 1]);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (cur >= 0 && active) {
+#pragma unroll
+        for (int k = 0; k < 2 * NPOL; k++) atomicAdd(&tile[k * PL + cur + loff], acc[k]);
+    }
+    __syncthreads();
+    flush_tile<NPOL>(a, tile, flush, tx0, ty0, h, R, STR, PL);
+}
+
+template <int NPOL>
+__global__ __launch_bounds__(1024) void k_grid_scatter(GridArgs a, int flush) {
+    extern __shared__ __align__(16) float smem[];
+    const int nthreads = blockDim.x, tid = threadIdx.x;
+    const WorkItem wk = a.work[blockIdx.x];
+    const int T = a.T, W = a.W, h = (W - 1) / 2, R = T + W - 1, STR = a.str, PL = a.plane;
+    const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
+    float *tile = smem;
+    float *tab = smem + 2 * NPOL * PL;
+    for (int i = tid; i < 2 * NPOL * PL; i += nthreads) tile[i] = 0.0f;
+    for (int i = tid; i < a.O * W; i += nthreads) tab[i] = a.tab[i];
+    __syncthreads();
+    for (int64_t i = wk.begin + tid; i < wk.end; i += nthreads) {
+        float2 v[NPOL];
+        load_vis<NPOL>(a.vis, a.perm[i], v);
+        apply_multiplier<NPOL>(a, i, v);
+        const uint32_t pp = a.spos[i];
+        const int cx = (int)(pp & 0xFFFu), cy = (int)((pp >> 12) & 0xFFFu);
+        const int px = (int)((pp >> 24) & 0xFu), py = (int)(pp >> 28);
+        const int o = (cy - ty0) * STR + (cx - tx0);
+        for (int sy = 0; sy < W; sy++) {
+            const float ty = tab[py * W + sy];
+            for (int sx = 0; sx < W; sx++) {
+                const float tap = ty * tab[px * W + sx];
+                const int c = o + sy * STR + sx;
+#pragma unroll
+                for (int p = 0; p < NPOL; p++) {
+                    atomicAdd(&tile[(2 * p) * PL + c], tap * v[p].x);
+                    atomicAdd(&tile[(2 * p + 1) * PL + c], tap * v[p].y);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    flush_tile<NPOL>(a, tile, flush, tx0, ty0, h, R, STR, PL);
+}
+
+// Merge pass of flush 2: every grid cell sums the partial tiles of all work items whose
+// (haloed) tile covers it, in a fixed order.
+template <int NPOL>
+__global__ void k_merge(float2 *grid, const float *partial, const int32_t *tile_work,
+                        const int32_t *work_ids, int nx, int ny, int T, int ntx, int nty, int W,
+                        int accumulate) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    const int h = (W - 1) / 2, R = T + W - 1;
+    float acc[2 * NPOL];
+#pragma unroll
+    for (int q = 0; q < 2 * NPOL; q++) acc[q] = 0.0f;
+    const int txc = x / T, tyc = y / T;
+    for (int dy = -1; dy <= 1; dy++) {
+        const int tty = tyc + dy;
+        if (tty < 0 || tty >= nty) continue;
+        const int r = y - (tty * T - h);
+        if (r < 0 || r >= R) continue;
+        for (int dx = -1; dx <= 1; dx++) {
+            const int ttx = txc + dx;
+            if (ttx < 0 || ttx >= ntx) continue;
+            const int c = x - (ttx * T - h);
+            if (c < 0 || c >= R) continue;
+            const int t = tty * ntx + ttx;
+            for (int k = tile_work[t]; k < tile_work[t + 1]; k++) {
+                const float *src = partial + (int64_t)work_ids[k] * (2 * NPOL) * R * R + r * R + c;
+#pragma unroll
+                for (int q = 0; q < 2 * NPOL; q++) acc[q] += src[(int64_t)q * R * R];
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NPOL; p++) {
+        float2 *dst = grid + ((int64_t)p * ny + y) * nx + x;
+        float2 v = make_float2(acc[2 * p], acc[2 * p + 1]);
+        if (accumulate) {
+            const float2 o = *dst;
+            v.x += o.x;
+            v.y += o.y;
+        }
+        *dst = v;
+    }
+}
+
+template <int NPOL>
+Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s) {
+    const Launch &L = I.L;
+    const int R = L.tile + I.W - 1;
+    a.str = tile_stride(R, I.W);
+    a.plane = tile_plane(R, a.str);
+    const int flush = L.flush;
+    if (flush == 2 && !I.partial) {
+        void *p;
+        MWG_TRY(I.arena.alloc(&p, sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * NPOL * R * R));
+        I.partial = (float *)p;
+    }
+    a.partial = I.partial;
+    if (flush == 1 && !accumulate)
+        MWG_TRY(launch_fill_zero(a.grid, sizeof(float2) * (size_t)NPOL * I.nx * I.ny, s));
+    if (I.nwork > 0) {
+        if (L.variant == 1) {
+            const size_t lds = taplanes_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
+            if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
+            hipLaunchKernelGGL(k_grid_taplanes<NPOL>, dim3(I.nwork), dim3(64 * L.wg_waves), lds, s, a, flush);
+        } else {
+            const size_t lds = scatter_lds(NPOL, L.tile, I.W, I.O);
+            if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
+            hipLaunchKernelGGL(k_grid_scatter<NPOL>, dim3(I.nwork), dim3(64 * L.wg_waves), lds, s, a, flush);
+        }
+        MWG_HIP(hipGetLastError());
+    }
+    if (flush == 2) {
+        dim3 blk(256), grd((I.nx + 255) / 256, I.ny);
+        hipLaunchKernelGGL(k_merge<NPOL>, grd, blk, 0, s, a.grid, (const float *)I.partial,
+                           (const int32_t *)I.tile_work, (const int32_t *)I.work_ids, I.nx, I.ny,
+                           L.tile, I.ntx, I.nty, I.W, accumulate);
+        MWG_HIP(hipGetLastError());
+    }
+    return Status::Ok();
+}
+
+} // namespace
+
+size_t taplanes_lds(int npol, int T, int W, int O, int waves) {
+    const int R = T + W - 1, STR = tile_stride(R, W), PL = tile_plane(R, STR);
+    return 4 * ((size_t)2 * npol * PL + (size_t)O * O * 64) + (size_t)waves * 64 * (8 * npol);
+}
+
+size_t scatter_lds(int npol, int T, int W, int O) {
+    const int R = T + W - 1, STR = tile_stride(R, W), PL = tile_plane(R, STR);
+    return 4 * ((size_t)2 * npol * PL + (size_t)O * W);
+}
+
+Status launch_fill_zero(void *ptr, size_t nbytes, hipStream_t s) {
+    if (nbytes == 0) return Status::Ok();
+    if (((uintptr_t)ptr % 16) == 0 && nbytes % 16 == 0) {
+        const int64_t n4 = (int64_t)(nbytes / 16);
+        const int64_t blocks = std::min<int64_t>((n4 + kFillBlock - 1) / kFillBlock, 1 << 16);
+        hipLaunchKernelGGL(k_fill_zero4, dim3((unsigned)blocks), dim3(kFillBlock), 0, s, (float4 *)ptr, n4);
+    } else {
+        const int64_t n = (int64_t)(nbytes / 4);
+        hipLaunchKernelGGL(k_fill_zero1, dim3((unsigned)((n + kFillBlock - 1) / kFillBlock)),
+                           dim3(kFillBlock), 0, s, (float *)ptr, n);
+    }
+    MWG_HIP(hipGetLastError());
+    return Status::Ok();
+}
+
+Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *grid, int accumulate,
+                   hipStream_t s) {
+    GridArgs a{};
+    a.vis = vis;
+    a.perm = I.perm;
+    a.spos = I.spos;
+    a.sant = I.sant;
+    a.sw = I.sw;
+    a.gains = gains;
+    a.work = I.work;
+    a.taps2d = I.taps2d;
+    a.tab = I.tab;
+    a.grid = grid;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.T = I.L.tile;
+    a.ntx = I.ntx;
+    a.W = I.W;
+    a.O = I.O;
+    switch (I.npol) {
+    case 1: return launch_grid_npol<1>(I, a, accumulate, s);
+    case 2: return launch_grid_npol<2>(I, a, accumulate, s);
+    case 4: return launch_grid_npol<4>(I, a, accumulate, s);
+    default: return make_error(MW_ERR_UNSUPPORTED, "npol %d", I.npol);
+    }
+}
+
+} // namespace mwg

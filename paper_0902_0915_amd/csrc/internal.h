@@ -1,0 +1,151 @@
+// Internal declarations of libmwagrid (not installed; the public ABI is include/mwagrid.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mwagrid.h"
+
+namespace mwg {
+
+// ------------------------------------------------------------------------------------------
+// Errors: every internal step returns a Status; the ABI layer turns it into mw_status and
+// records the message for mw_last_error().
+// ------------------------------------------------------------------------------------------
+struct Status {
+    mw_status code = MW_OK;
+    std::string msg;
+    bool ok() const { return code == MW_OK; }
+    static Status Ok() { return {}; }
+};
+Status make_error(mw_status code, const char *fmt, ...);
+
+#define MWG_HIP(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::mwg::make_error(MW_ERR_HIP, "%s failed: %s (%s:%d)", #expr,             \
+                                     hipGetErrorString(e_), __FILE__, __LINE__);              \
+    } while (0)
+
+#define MWG_TRY(expr)                                                                         \
+    do {                                                                                      \
+        ::mwg::Status s_ = (expr);                                                            \
+        if (!s_.ok()) return s_;                                                              \
+    } while (0)
+
+// Device allocation tracked per instance so that plan_bytes can be reported.
+struct DevArena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    Status alloc(void **p, size_t nbytes);
+    void release();
+};
+
+// Packed per-group position: cx | cy << 12 | (px + O/2) << 24 | (py + O/2) << 28.
+constexpr uint32_t kDropped = 0xFFFFFFFFu;
+__host__ __device__ inline uint32_t pack_pos(int cx, int cy, int pxo, int pyo) {
+    return (uint32_t)cx | ((uint32_t)cy << 12) | ((uint32_t)pxo << 24) | ((uint32_t)pyo << 28);
+}
+
+// Launch configuration of the gridder / degridder for one instance.
+struct Launch {
+    int tile = 32;     // T (power of two)
+    int split = 8192;  // max groups per work item
+    int wg_waves = 8;  // waves per workgroup
+    int order = 1;     // 1 cell-sorted, 2 input order within tile
+    int variant = 1;   // gridder variant
+    int flush = 1;     // 1 atomic, 2 deterministic merge
+};
+
+struct WorkItem {
+    int32_t tile, begin, end, pad;
+};
+
+struct Instance {
+    // description (copied from mw_instance)
+    int nx = 0, ny = 0, npol = 1, nchan = 1, W = 0, O = 1, h = 0, nant = 0;
+    int64_t nrow = 0, ngroups = 0;
+    double du = 0, dv = 0;
+    bool stacks = false, has_weights = false, has_ants = false;
+    int nkernel = 0, max_support = 0;
+    // counts
+    int64_t nkept = 0, nflagged = 0, noutside = 0;
+    // launch
+    Launch L;
+    int ntx = 0, nty = 0, ntiles_nonempty = 0, nwork = 0;
+    int max_work_groups = 0;  // largest work item
+    // device arrays (owned by arena)
+    DevArena arena;
+    uint32_t *pos = nullptr;      // [ngroups] packed, original order
+    uint32_t *perm = nullptr;     // [nkept] sorted -> original group
+    uint32_t *spos = nullptr;     // [nkept] packed, sorted
+    float *sw = nullptr;          // [nkept] weights, sorted (or null)
+    uint32_t *sant = nullptr;     // [nkept] ant1 | ant2 << 16, sorted (or null)
+    uint32_t *skid = nullptr;     // [nkept] kernel id, sorted (stacks)
+    uint32_t *dropped = nullptr;  // [ngroups - nkept] original indices of dropped groups
+    WorkItem *work = nullptr;     // [nwork]
+    int32_t *tile_work = nullptr; // [ntiles + 1] CSR: work items of each tile (merge flush)
+    int32_t *work_ids = nullptr;  // [nwork] work item ids grouped by tile
+    float *partial = nullptr;     // merge flush scratch: [nwork][2*npol][R*R]
+    float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)
+    float *tab = nullptr;         // [O][W]
+    float *corrx = nullptr, *corry = nullptr;
+    float2 *kstack = nullptr;     // stacks: complex taps
+    int64_t *koff = nullptr;
+    int32_t *ksup = nullptr;
+    // host copies for export
+    std::vector<float> h_tab, h_corrx, h_corry;
+    // image plans (rocFFT); opaque here
+    void *fft = nullptr;
+};
+
+struct Plan {
+    int device = 0;
+    std::vector<Instance *> inst;
+    // batched form (ninst > 1)
+    void *batch = nullptr;
+};
+
+// pswf.cpp
+void prolate_tables(int W, int O, int nx, int ny, std::vector<float> &table,
+                    std::vector<float> &corr_x, std::vector<float> &corr_y);
+
+// plan.hip
+Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *t, hipStream_t s);
+Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s);
+
+// grid.hip
+Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *grid,
+                   int accumulate, hipStream_t s);
+Status launch_fill_zero(void *ptr, size_t nbytes, hipStream_t s);
+
+// degrid.hip
+Status launch_degrid(Instance &I, const float2 *grid, const float2 *gains, const float2 *vis_in,
+                     float2 *vis_out, float2 *grad_gains, hipStream_t s);
+
+// image.cpp / image.hip
+Status image_prepare(Instance &I);
+Status launch_image(Instance &I, const float2 *in, float2 *out, int direction, int correct,
+                    hipStream_t s);
+void image_release(Instance &I);
+Status launch_image_scale(const float2 *in, float2 *out, int nx, int ny, int npol,
+                          const float *corrx, const float *corry, int checker, int divide,
+                          hipStream_t s);
+
+// batched.cpp
+Status batch_prepare(Plan &P, hipStream_t s);
+Status batch_grid(Plan &P, const void *const *vis, const void *const *gains, void *const *grid,
+                  int accumulate, hipStream_t s);
+Status batch_degrid(Plan &P, const void *const *grid, const void *const *gains,
+                    const void *const *vis_in, void *const *vis_out, void *const *grad_gains,
+                    hipStream_t s);
+void batch_release(Plan &P);
+
+// tuner.cpp
+Status autotune(Instance &I, hipStream_t s);
+
+} // namespace mwg

@@ -1,0 +1,676 @@
+// Plan construction: FP64 positions and quantisation, the keep rule, the stable radix sort
+// by uv tile (and cell), tile bounds, the heavy-tile split into work items, and the
+// kernel tables.
+//
+// The paper says the GPU port needed new memory structures and some algorithmic changes to
+// suit the hardware's access-pattern sensitivity (Section 3.2). Here that is the plan: the
+// visibilities' positions never change between calls, so they are computed, quantised and
+// sorted by grid tile once, and every later grid/degrid call walks the sorted order.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace mwg {
+
+Status make_error(mw_status code, const char *fmt, ...) {
+    Status s;
+    s.code = code;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    s.msg = buf;
+    return s;
+}
+
+Status DevArena::alloc(void **p, size_t nbytes) {
+    *p = nullptr;
+    if (nbytes == 0) nbytes = 16;
+    hipError_t e = hipMalloc(p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
+    }
+    ptrs.push_back(*p);
+    bytes += (int64_t)nbytes;
+    return Status::Ok();
+}
+
+void DevArena::release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+}
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Temporary device buffer freed at scope exit.
+struct Tmp {
+    void *p = nullptr;
+    ~Tmp() {
+        if (p) (void)hipFree(p);
+    }
+    Status alloc(size_t n) {
+        hipError_t e = hipMalloc(&p, n ? n : 16);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+        }
+        return Status::Ok();
+    }
+    template <class T> T *as() { return (T *)p; }
+};
+
+// ------------------------------------------------------------------------------------------
+// A1: positions. One thread per group; every operation rounded to FP64 in the stated order
+// (no contraction), so the integers agree bit for bit with any IEEE FP64 evaluation of the
+// same rule.
+// ------------------------------------------------------------------------------------------
+struct PosArgs {
+    int64_t ngroups;
+    int nchan, nx, ny, O, h;
+    double du, dv;
+    const double *uvw, *freq;
+    const uint8_t *flags;
+    const float *weights;
+    const int32_t *kidx;   // stacks: kernel of each group
+    const int32_t *ksup;   // stacks: support of each kernel
+    uint32_t *pos;
+    unsigned long long *counts; // kept, flagged, outside
+};
+
+__global__ void k_positions(PosArgs a) {
+#pragma clang fp contract(off)
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int status = 3; // 0 kept, 1 flagged, 2 outside, 3 out of range
+    if (g < a.ngroups) {
+        uint32_t packed = kDropped;
+        if ((a.flags && a.flags[g]) || (a.weights && a.weights[g] == 0.0f)) {
+            status = 1;
+        } else {
+            const int64_t r = g / a.nchan;
+            const int ch = (int)(g - r * a.nchan);
+            const double f = a.freq[ch];
+            const double u = (a.uvw[3 * r + 0] * f) / 299792458.0;
+            const double v = (a.uvw[3 * r + 1] * f) / 299792458.0;
+            const double x = u / a.du + (double)(a.nx / 2);
+            const double y = v / a.dv + (double)(a.ny / 2);
+            const double qxd = floor(x * (double)a.O + 0.5);
+            const double qyd = floor(y * (double)a.O + 0.5);
+            status = 2;
+            if (fabs(qxd) < 1e15 && fabs(qyd) < 1e15) {
+                const int64_t qx = (int64_t)qxd, qy = (int64_t)qyd;
+                const int64_t half = a.O / 2;
+                int64_t cx = (qx + half) / a.O, cy = (qy + half) / a.O;
+                if ((qx + half) % a.O != 0 && (qx + half) < 0) cx -= 1; // floor division
+                if ((qy + half) % a.O != 0 && (qy + half) < 0) cy -= 1;
+                const int64_t px = qx - cx * a.O, py = qy - cy * a.O;
+                const int h = a.kidx ? (a.ksup[a.kidx[g]] - 1) / 2 : a.h;
+                if (cx - h >= 0 && cx + h < a.nx && cy - h >= 0 && cy + h < a.ny) {
+                    packed = pack_pos((int)cx, (int)cy, (int)(px + half), (int)(py + half));
+                    status = 0;
+                }
+            }
+        }
+        a.pos[g] = packed;
+    }
+    // one atomic per wave and category
+    const unsigned long long k0 = __ballot(status == 0), k1 = __ballot(status == 1),
+                             k2 = __ballot(status == 2);
+    if ((threadIdx.x & 63) == 0) {
+        if (k0) atomicAdd(&a.counts[0], (unsigned long long)__popcll(k0));
+        if (k1) atomicAdd(&a.counts[1], (unsigned long long)__popcll(k1));
+        if (k2) atomicAdd(&a.counts[2], (unsigned long long)__popcll(k2));
+    }
+}
+
+// Sort keys: tile-major, then cell within the tile (order 1) or nothing (order 2: the stable
+// sort keeps input order). Dropped groups get the all-ones key of the sorted width.
+__global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int order,
+                       uint32_t sentinel, uint32_t *keys) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const uint32_t p = pos[g];
+    uint32_t k = sentinel;
+    if (p != kDropped) {
+        const uint32_t cx = p & 0xFFFu, cy = (p >> 12) & 0xFFFu;
+        const uint32_t tile = (cy >> tb) * (uint32_t)ntx + (cx >> tb);
+        const uint32_t mask = (1u << tb) - 1u;
+        k = order == 1 ? (tile << (2 * tb)) | ((cy & mask) << tb) | (cx & mask) : tile;
+    }
+    keys[g] = k;
+}
+
+// ------------------------------------------------------------------------------------------
+// A2: stable LSD radix sort of (key, index) pairs, 8 bits per pass.
+//   hist:    per block digit counts, stored digit-major [256][nblocks]
+//   scan:    exclusive prefix over that array -> each (digit, block) output base
+//   scatter: each block ranks its keys stably (wave ballots for equal digits, waves in
+//            order) and writes them at base + rank.
+// ------------------------------------------------------------------------------------------
+constexpr int kSortItems = 16;                 // keys per thread per block
+constexpr int kSortChunk = kBlock * kSortItems; // keys per block
+
+__global__ void k_rs_hist(const uint32_t *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    for (int it = 0; it < kSortItems; it++) {
+        const int64_t i = base + (int64_t)it * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                             uint32_t *vals_out, const uint32_t *offsets, int64_t n, int shift,
+                             int nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    run[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+    for (int w = 0; w < kBlock / 64; w++) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kSortItems; it++) {
+        const int64_t i = base + (int64_t)it * kBlock + tid;
+        const bool valid = i < n;
+        const uint32_t k = valid ? keys_in[i] : 0u;
+        const uint32_t d = (k >> shift) & 255u;
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & below);
+        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[d] + (uint32_t)rank;
+            for (int w = 0; w < wave; w++) off += wcnt[w][d];
+            keys_out[off] = k;
+            vals_out[off] = vals_in ? vals_in[i] : (uint32_t)i;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int w = 0; w < kBlock / 64; w++) {
+            tot += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of uint32 (totals < 2^32): 1024 items per block, block sums scanned
+// recursively, then added back.
+constexpr int kScanItems = 4;
+constexpr int kScanChunk = kBlock * kScanItems;
+
+__global__ void k_scan_block(uint32_t *data, int64_t n, uint32_t *sums) {
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)tid * kScanItems;
+    uint32_t v[kScanItems], t = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        v[j] = (base + j < n) ? data[base + j] : 0u;
+        t += v[j];
+    }
+    // inclusive scan of t across the wave
+    uint32_t inc = t;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < wave; w++) wbase += wsum[w];
+    uint32_t run = wbase + inc - t;
+    for (int j = 0; j < kScanItems; j++) {
+        if (base + j < n) data[base + j] = run;
+        run += v[j];
+    }
+    if (tid == kBlock - 1) sums[blockIdx.x] = wbase + inc;
+}
+
+__global__ void k_scan_add(uint32_t *data, int64_t n, const uint32_t *sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const uint32_t add = sums[blockIdx.x];
+    for (int j = 0; j < kScanItems; j++)
+        if (base + j < n) data[base + j] += add;
+}
+
+Status scan_exclusive(uint32_t *data, int64_t n, hipStream_t s) {
+    if (n <= 0) return Status::Ok();
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    Tmp sums;
+    MWG_TRY(sums.alloc(sizeof(uint32_t) * nb));
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n,
+                       sums.as<uint32_t>());
+    MWG_HIP(hipGetLastError());
+    if (nb > 1) {
+        MWG_TRY(scan_exclusive(sums.as<uint32_t>(), nb, s));
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n,
+                           sums.as<uint32_t>());
+        MWG_HIP(hipGetLastError());
+    }
+    // sums must outlive the kernels that read it
+    MWG_HIP(hipStreamSynchronize(s));
+    return Status::Ok();
+}
+
+// Sorts (keys, implicit index) by the low keybits bits; result in keys_out/vals_out.
+Status radix_sort(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
+                  int64_t n, int keybits, uint32_t **keys_out, uint32_t **vals_out,
+                  hipStream_t s) {
+    const int nblocks = (int)((n + kSortChunk - 1) / kSortChunk);
+    Tmp hist;
+    MWG_TRY(hist.alloc(sizeof(uint32_t) * 256 * (size_t)std::max(nblocks, 1)));
+    uint32_t *kin = keys, *kout = keys_alt, *vin = nullptr, *vout = vals;
+    const int passes = (keybits + 7) / 8;
+    for (int p = 0; p < passes; p++) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift,
+                           hist.as<uint32_t>(), nblocks);
+        MWG_HIP(hipGetLastError());
+        MWG_TRY(scan_exclusive(hist.as<uint32_t>(), (int64_t)256 * nblocks, s));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kBlock), 0, s, kin, vin, kout, vout,
+                           hist.as<uint32_t>(), n, shift, nblocks);
+        MWG_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        vin = vout;
+        vout = (vout == vals) ? vals_alt : vals;
+    }
+    if (passes == 0) return make_error(MW_ERR_UNSUPPORTED, "empty sort key");
+    *keys_out = kin;
+    *vals_out = vin;
+    MWG_HIP(hipStreamSynchronize(s));
+    return Status::Ok();
+}
+
+__global__ void k_tile_bounds(const uint32_t *skeys, int64_t nkept, int cellbits, int32_t *tstart,
+                              int32_t *tend) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nkept) return;
+    const uint32_t t = skeys[i] >> cellbits;
+    if (i == 0 || (skeys[i - 1] >> cellbits) != t) tstart[t] = (int32_t)i;
+    if (i == nkept - 1 || (skeys[i + 1] >> cellbits) != t) tend[t] = (int32_t)(i + 1);
+}
+
+__global__ void k_gather(const uint32_t *perm, int64_t nkept, int nchan, const uint32_t *pos,
+                         const float *weights, const int32_t *ant1, const int32_t *ant2,
+                         const int32_t *kidx, uint32_t *spos, float *sw, uint32_t *sant,
+                         uint32_t *skid) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nkept) return;
+    const uint32_t g = perm[i];
+    spos[i] = pos[g];
+    if (sw) sw[i] = weights[g];
+    if (sant) {
+        const int64_t r = (int64_t)g / nchan;
+        sant[i] = (uint32_t)ant1[r] | ((uint32_t)ant2[r] << 16);
+    }
+    if (skid) skid[i] = (uint32_t)kidx[g];
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int ilog2(int v) {
+    int r = 0;
+    while ((1 << r) < v) r++;
+    return r;
+}
+
+int bitlength(uint64_t v) {
+    int r = 0;
+    while (v) {
+        r++;
+        v >>= 1;
+    }
+    return r;
+}
+
+unsigned grid1d(int64_t n, int block = kBlock) { return (unsigned)((n + block - 1) / block); }
+
+// Copy a caller array to the device (host source) or use it in place (device source).
+template <class T>
+Status stage_input(const T *src, size_t count, int mem, Tmp &tmp, const T **dst, hipStream_t s) {
+    *dst = nullptr;
+    if (!src) return Status::Ok();
+    if (mem == MW_MEM_DEVICE) {
+        *dst = src;
+        return Status::Ok();
+    }
+    MWG_TRY(tmp.alloc(sizeof(T) * count));
+    MWG_HIP(hipMemcpyAsync(tmp.p, src, sizeof(T) * count, hipMemcpyHostToDevice, s));
+    *dst = (const T *)tmp.p;
+    return Status::Ok();
+}
+
+} // namespace
+
+Status launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return Status::Ok();
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid1d(n)), dim3(kBlock), 0, s, p, n, v);
+    MWG_HIP(hipGetLastError());
+    return Status::Ok();
+}
+
+// ------------------------------------------------------------------------------------------
+// Work list: sort by (tile[, cell]), tile bounds, split heavy tiles, largest first.
+// Rebuilt when the tuner changes the tile size, order or split.
+// ------------------------------------------------------------------------------------------
+Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
+    const int64_t ng = I.ngroups;
+    const int tb = ilog2(L.tile);
+    if ((1 << tb) != L.tile) return make_error(MW_ERR_INVALID_ARG, "tile %d is not a power of two", L.tile);
+    const int ntx = (I.nx + L.tile - 1) / L.tile, nty = (I.ny + L.tile - 1) / L.tile;
+    const int64_t ntiles = (int64_t)ntx * nty;
+    const int cellbits = L.order == 1 ? 2 * tb : 0;
+    const uint64_t maxkey = (uint64_t)ntiles << cellbits; // exclusive bound of valid keys
+    const int keybits = bitlength(maxkey);
+    if (keybits > 31) return make_error(MW_ERR_UNSUPPORTED, "sort key wider than 31 bits");
+    const uint32_t sentinel = (keybits >= 32) ? 0xFFFFFFFFu : ((1u << keybits) - 1u);
+
+    Tmp keys, keys2, vals, vals2;
+    MWG_TRY(keys.alloc(4 * ng));
+    MWG_TRY(keys2.alloc(4 * ng));
+    MWG_TRY(vals.alloc(4 * ng));
+    MWG_TRY(vals2.alloc(4 * ng));
+    uint32_t *skeys = nullptr, *sperm = nullptr;
+    if (ng > 0) {
+        hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, L.order,
+                           sentinel, keys.as<uint32_t>());
+        MWG_HIP(hipGetLastError());
+        MWG_TRY(radix_sort(keys.as<uint32_t>(), keys2.as<uint32_t>(), vals.as<uint32_t>(),
+                           vals2.as<uint32_t>(), ng, keybits, &skeys, &sperm, s));
+        MWG_HIP(hipMemcpyAsync(I.perm, sperm, 4 * ng, hipMemcpyDeviceToDevice, s));
+    }
+    const int64_t nk = I.nkept;
+    // tile bounds
+    Tmp tstart, tend;
+    MWG_TRY(tstart.alloc(4 * ntiles));
+    MWG_TRY(tend.alloc(4 * ntiles));
+    MWG_TRY(launch_fill_u32(tstart.as<uint32_t>(), ntiles, 0, s));
+    MWG_TRY(launch_fill_u32(tend.as<uint32_t>(), ntiles, 0, s));
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_tile_bounds, dim3(grid1d(nk)), dim3(kBlock), 0, s, skeys, nk,
+                           cellbits, tstart.as<int32_t>(), tend.as<int32_t>());
+        MWG_HIP(hipGetLastError());
+    }
+    std::vector<int32_t> hs(ntiles), he(ntiles);
+    MWG_HIP(hipMemcpyAsync(hs.data(), tstart.p, 4 * ntiles, hipMemcpyDeviceToHost, s));
+    MWG_HIP(hipMemcpyAsync(he.data(), tend.p, 4 * ntiles, hipMemcpyDeviceToHost, s));
+    MWG_HIP(hipStreamSynchronize(s));
+
+    std::vector<WorkItem> items;
+    int nonempty = 0;
+    for (int64_t t = 0; t < ntiles; t++) {
+        const int64_t cnt = he[t] - hs[t];
+        if (cnt <= 0) continue;
+        nonempty++;
+        const int64_t pieces = (cnt + L.split - 1) / L.split;
+        for (int64_t q = 0; q < pieces; q++) {
+            WorkItem w;
+            w.tile = (int32_t)t;
+            w.begin = (int32_t)(hs[t] + cnt * q / pieces);
+            w.end = (int32_t)(hs[t] + cnt * (q + 1) / pieces);
+            w.pad = 0;
+            items.push_back(w);
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const WorkItem &a, const WorkItem &b) {
+        return (a.end - a.begin) > (b.end - b.begin);
+    });
+    // CSR of work items per tile (for the deterministic merge flush)
+    std::vector<int32_t> tw(ntiles + 1, 0), ids(items.size());
+    for (const WorkItem &w : items) tw[w.tile + 1]++;
+    for (int64_t t = 0; t < ntiles; t++) tw[t + 1] += tw[t];
+    {
+        std::vector<int32_t> fillp(tw.begin(), tw.end() - 1);
+        for (size_t i = 0; i < items.size(); i++) ids[fillp[items[i].tile]++] = (int32_t)i;
+    }
+    // (re)allocate schedule arrays: these are small; keep them in the arena
+    I.L = L;
+    I.ntx = ntx;
+    I.nty = nty;
+    I.ntiles_nonempty = nonempty;
+    I.nwork = (int)items.size();
+    I.max_work_groups = 0;
+    for (const WorkItem &w : items) I.max_work_groups = std::max(I.max_work_groups, w.end - w.begin);
+    void *p;
+    MWG_TRY(I.arena.alloc(&p, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)));
+    I.work = (WorkItem *)p;
+    MWG_TRY(I.arena.alloc(&p, 4 * (ntiles + 1)));
+    I.tile_work = (int32_t *)p;
+    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(ids.size(), 1)));
+    I.work_ids = (int32_t *)p;
+    if (!items.empty())
+        MWG_HIP(hipMemcpyAsync(I.work, items.data(), sizeof(WorkItem) * items.size(),
+                               hipMemcpyHostToDevice, s));
+    MWG_HIP(hipMemcpyAsync(I.tile_work, tw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
+    if (!ids.empty())
+        MWG_HIP(hipMemcpyAsync(I.work_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
+    MWG_HIP(hipStreamSynchronize(s));
+    return Status::Ok();
+}
+
+size_t taplanes_lds(int npol, int T, int W, int O, int waves);
+size_t scatter_lds(int npol, int T, int W, int O);
+
+static Launch default_launch(const Instance &I) {
+    Launch L;
+    // LDS tile (T + W - 1)^2 * 2 * npol floats must fit beside the tap table and staging.
+    const int W = I.stacks ? I.max_support : I.W;
+    if (I.stacks) {
+        L.tile = 64;
+        L.variant = 3;
+    } else if (I.npol >= 4) {
+        L.tile = 32;
+    } else if (I.npol == 2) {
+        L.tile = 32;
+    } else {
+        L.tile = 64;
+    }
+    (void)W;
+    L.split = 8192;
+    L.wg_waves = 8;
+    L.order = 1;
+    L.flush = 1;
+    if (!I.stacks) L.variant = (I.W * I.W <= 64) ? 1 : 3;
+    return L;
+}
+
+// Default launch overridden by the caller's non-zero tuning fields, checked against the
+// kernels' limits (LDS, lanes).
+Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
+    Launch L = default_launch(I);
+    if (t) {
+        if (t->tile) L.tile = t->tile;
+        if (t->split) L.split = t->split;
+        if (t->wg_waves) L.wg_waves = t->wg_waves;
+        if (t->order) L.order = t->order;
+        if (t->variant) L.variant = t->variant;
+        if (t->flush) L.flush = t->flush;
+    }
+    if (!I.stacks) {
+        if (L.variant == 2) return make_error(MW_ERR_UNSUPPORTED, "gridder variant 2 is not built");
+        if (L.variant == 1 && I.W * I.W > 64)
+            return make_error(MW_ERR_UNSUPPORTED, "variant 1 needs W*W <= 64 (W = %d)", I.W);
+        const size_t lds = L.variant == 1 ? taplanes_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
+                                          : scatter_lds(I.npol, L.tile, I.W, I.O);
+        if (lds > 160 * 1024)
+            return make_error(MW_ERR_UNSUPPORTED, "launch needs %zu B of LDS (tile %d, npol %d)", lds,
+                              L.tile, I.npol);
+    }
+    *out = L;
+    return Status::Ok();
+}
+
+Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning, hipStream_t s) {
+    I.nx = d.nx;
+    I.ny = d.ny;
+    I.du = d.du;
+    I.dv = d.dv;
+    I.nrow = d.nrow;
+    I.nchan = d.nchan;
+    I.npol = d.npol;
+    I.ngroups = d.nrow * d.nchan;
+    I.O = d.oversample;
+    I.stacks = d.kernel_stack != nullptr;
+    I.W = I.stacks ? 0 : d.support;
+    I.h = I.stacks ? 0 : (d.support - 1) / 2;
+    I.has_weights = d.weights != nullptr;
+    I.has_ants = d.ant1 != nullptr;
+    I.nant = I.has_ants ? d.nant : 0;
+    const int64_t ng = I.ngroups;
+
+    // stage inputs
+    Tmp t_uvw, t_freq, t_flags, t_w, t_a1, t_a2, t_kidx, t_ksup;
+    const double *uvw, *freq;
+    const uint8_t *flags;
+    const float *weights;
+    const int32_t *a1, *a2, *kidx = nullptr, *ksup = nullptr;
+    MWG_TRY(stage_input(d.uvw_m, 3 * (size_t)d.nrow, d.mem, t_uvw, &uvw, s));
+    MWG_TRY(stage_input(d.freq_hz, (size_t)d.nchan, d.mem, t_freq, &freq, s));
+    MWG_TRY(stage_input(d.flags, (size_t)ng, d.mem, t_flags, &flags, s));
+    MWG_TRY(stage_input(d.weights, (size_t)ng, d.mem, t_w, &weights, s));
+    MWG_TRY(stage_input(d.ant1, (size_t)d.nrow, d.mem, t_a1, &a1, s));
+    MWG_TRY(stage_input(d.ant2, (size_t)d.nrow, d.mem, t_a2, &a2, s));
+    void *p;
+    if (I.stacks) {
+        I.nkernel = d.nkernel;
+        MWG_TRY(stage_input(d.kernel_index, (size_t)ng, d.mem, t_kidx, &kidx, s));
+        MWG_TRY(stage_input(d.kernel_support, (size_t)d.nkernel, d.mem, t_ksup, &ksup, s));
+        MWG_TRY(I.arena.alloc(&p, 8 * (size_t)d.kernel_elems));
+        I.kstack = (float2 *)p;
+        MWG_HIP(hipMemcpyAsync(I.kstack, d.kernel_stack, 8 * (size_t)d.kernel_elems,
+                               d.mem == MW_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        MWG_TRY(I.arena.alloc(&p, 8 * (size_t)d.nkernel));
+        I.koff = (int64_t *)p;
+        MWG_HIP(hipMemcpyAsync(I.koff, d.kernel_offset, 8 * (size_t)d.nkernel,
+                               d.mem == MW_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)d.nkernel));
+        I.ksup = (int32_t *)p;
+        MWG_HIP(hipMemcpyAsync(I.ksup, d.kernel_support, 4 * (size_t)d.nkernel,
+                               d.mem == MW_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        std::vector<int32_t> hsup(d.nkernel);
+        MWG_HIP(hipMemcpyAsync(hsup.data(), I.ksup, 4 * (size_t)d.nkernel, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipStreamSynchronize(s));
+        I.max_support = 0;
+        for (int v : hsup) {
+            if (v < 1 || v > 63 || v % 2 == 0)
+                return make_error(MW_ERR_INVALID_ARG, "kernel support %d must be odd in [1, 63]", v);
+            I.max_support = std::max(I.max_support, v);
+        }
+    }
+
+    // A1: positions
+    MWG_TRY(I.arena.alloc(&p, 4 * (size_t)ng));
+    I.pos = (uint32_t *)p;
+    Tmp counts;
+    MWG_TRY(counts.alloc(3 * sizeof(unsigned long long)));
+    MWG_TRY(launch_fill_u32(counts.as<uint32_t>(), 6, 0, s));
+    PosArgs a;
+    a.ngroups = ng;
+    a.nchan = I.nchan;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.O = I.O;
+    a.h = I.h;
+    a.du = I.du;
+    a.dv = I.dv;
+    a.uvw = uvw;
+    a.freq = freq;
+    a.flags = flags;
+    a.weights = weights;
+    a.kidx = kidx;
+    a.ksup = ksup;
+    a.pos = I.pos;
+    a.counts = counts.as<unsigned long long>();
+    if (ng > 0) {
+        hipLaunchKernelGGL(k_positions, dim3(grid1d(ng)), dim3(kBlock), 0, s, a);
+        MWG_HIP(hipGetLastError());
+    }
+    unsigned long long hc[3] = {0, 0, 0};
+    MWG_HIP(hipMemcpyAsync(hc, counts.p, sizeof hc, hipMemcpyDeviceToHost, s));
+    MWG_HIP(hipStreamSynchronize(s));
+    I.nkept = (int64_t)hc[0];
+    I.nflagged = (int64_t)hc[1];
+    I.noutside = (int64_t)hc[2];
+
+    // A2: sort + schedule (perm holds all ngroups: kept first, then dropped in input order)
+    MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(ng, 1)));
+    I.perm = (uint32_t *)p;
+    I.dropped = I.perm + I.nkept;
+    Launch L;
+    MWG_TRY(resolve_launch(I, tuning, &L));
+    MWG_TRY(rebuild_schedule(I, L, s));
+    const int64_t nk = I.nkept;
+    MWG_TRY(I.arena.alloc(&p, 4 * ((size_t)nk + 64)));  // + 64: the gridder reads ahead
+    I.spos = (uint32_t *)p;
+    if (I.has_weights) {
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(nk, 1)));
+        I.sw = (float *)p;
+    }
+    if (I.has_ants) {
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(nk, 1)));
+        I.sant = (uint32_t *)p;
+    }
+    if (I.stacks) {
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(nk, 1)));
+        I.skid = (uint32_t *)p;
+    }
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_gather, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.perm, nk, I.nchan,
+                           I.pos, weights, a1, a2, kidx, I.spos, I.sw, I.sant, I.skid);
+        MWG_HIP(hipGetLastError());
+    }
+
+    // A3: kernel tables (built-in kernel) and correction vectors
+    if (!I.stacks) {
+        prolate_tables(I.W, I.O, I.nx, I.ny, I.h_tab, I.h_corrx, I.h_corry);
+        std::vector<float> taps2d((size_t)I.O * I.O * 64, 0.0f);
+        if (I.W * I.W <= 64) {
+            for (int py = 0; py < I.O; py++)
+                for (int px = 0; px < I.O; px++)
+                    for (int sy = 0; sy < I.W; sy++)
+                        for (int tx = 0; tx < I.W; tx++)
+                            taps2d[((size_t)py * I.O + px) * 64 + sy * I.W + tx] =
+                                I.h_tab[(size_t)py * I.W + sy] * I.h_tab[(size_t)px * I.W + tx];
+        }
+        MWG_TRY(I.arena.alloc(&p, 4 * taps2d.size()));
+        I.taps2d = (float *)p;
+        MWG_HIP(hipMemcpyAsync(I.taps2d, taps2d.data(), 4 * taps2d.size(), hipMemcpyHostToDevice, s));
+        MWG_TRY(I.arena.alloc(&p, 4 * I.h_tab.size()));
+        I.tab = (float *)p;
+        MWG_HIP(hipMemcpyAsync(I.tab, I.h_tab.data(), 4 * I.h_tab.size(), hipMemcpyHostToDevice, s));
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)I.nx));
+        I.corrx = (float *)p;
+        MWG_HIP(hipMemcpyAsync(I.corrx, I.h_corrx.data(), 4 * (size_t)I.nx, hipMemcpyHostToDevice, s));
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)I.ny));
+        I.corry = (float *)p;
+        MWG_HIP(hipMemcpyAsync(I.corry, I.h_corry.data(), 4 * (size_t)I.ny, hipMemcpyHostToDevice, s));
+    }
+    MWG_HIP(hipStreamSynchronize(s));
+    return Status::Ok();
+}
+
+} // namespace mwg
