@@ -177,6 +177,9 @@ mw_status mw_grid(mw_plan plan, const void *const *vis, const void *const *gains
         for (int i = 0; i < n; i++) {
             if (!grid[i] || (!vis[i] && P->inst[i]->ngroups > 0))
                 return fail(MW_ERR_INVALID_ARG, "vis[i] and grid[i] must be device pointers");
+            const uintptr_t align = P->inst[i]->npol >= 2 ? 16 : 8;
+            if (((uintptr_t)vis[i] % align) || ((uintptr_t)grid[i] % 8))
+                return fail(MW_ERR_INVALID_ARG, "vis must be 16-byte aligned (8 for npol 1), grid 8-byte");
             if (gains && gains[i] && !P->inst[i]->has_ants)
                 return fail(MW_ERR_STATE, "gains given for an instance planned without antennas");
         }

@@ -320,10 +320,12 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
     a.str = tile_stride(R, I.W);
     a.plane = tile_plane(R, a.str);
     const int flush = L.flush;
-    if (flush == 2 && !I.partial) {
+    const size_t need = sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * NPOL * R * R;
+    if (flush == 2 && I.partial_bytes < need) {
         void *p;
-        MWG_TRY(I.arena.alloc(&p, sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * NPOL * R * R));
+        MWG_TRY(I.arena.alloc(&p, need));
         I.partial = (float *)p;
+        I.partial_bytes = need;
     }
     a.partial = I.partial;
     if (flush == 1 && !accumulate)

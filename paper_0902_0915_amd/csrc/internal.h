@@ -91,6 +91,7 @@ struct Instance {
     int32_t *tile_work = nullptr; // [ntiles + 1] CSR: work items of each tile (merge flush)
     int32_t *work_ids = nullptr;  // [nwork] work item ids grouped by tile
     float *partial = nullptr;     // merge flush scratch: [nwork][2*npol][R*R]
+    size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)
     float *tab = nullptr;         // [O][W]
     float *corrx = nullptr, *corry = nullptr;

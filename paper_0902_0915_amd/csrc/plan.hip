@@ -327,6 +327,15 @@ __global__ void k_gather(const uint32_t *perm, int64_t nkept, int nchan, const u
     if (skid) skid[i] = (uint32_t)kidx[g];
 }
 
+// Counts entries of an index array outside [0, limit).
+__global__ void k_count_out_of_range(const int32_t *idx, int64_t n, int32_t limit,
+                                     unsigned long long *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool out = i < n && (idx[i] < 0 || idx[i] >= limit);
+    const unsigned long long m = __ballot(out);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(bad, (unsigned long long)__popcll(m));
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -555,9 +564,31 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     MWG_TRY(stage_input(d.ant1, (size_t)d.nrow, d.mem, t_a1, &a1, s));
     MWG_TRY(stage_input(d.ant2, (size_t)d.nrow, d.mem, t_a2, &a2, s));
     void *p;
+    // Index arrays must stay inside the arrays they index (checked once, on the device).
+    {
+        Tmp bad;
+        MWG_TRY(bad.alloc(sizeof(unsigned long long)));
+        MWG_TRY(launch_fill_u32(bad.as<uint32_t>(), 2, 0, s));
+        if (a1 && d.nrow > 0) {
+            hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a1,
+                               (int64_t)d.nrow, d.nant, bad.as<unsigned long long>());
+            hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a2,
+                               (int64_t)d.nrow, d.nant, bad.as<unsigned long long>());
+            MWG_HIP(hipGetLastError());
+        }
+        if (I.stacks && ng > 0) {
+            MWG_TRY(stage_input(d.kernel_index, (size_t)ng, d.mem, t_kidx, &kidx, s));
+            hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(ng)), dim3(kBlock), 0, s, kidx, ng,
+                               d.nkernel, bad.as<unsigned long long>());
+            MWG_HIP(hipGetLastError());
+        }
+        unsigned long long hb = 0;
+        MWG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof hb, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipStreamSynchronize(s));
+        if (hb) return make_error(MW_ERR_INVALID_ARG, "%llu antenna or kernel indices out of range", hb);
+    }
     if (I.stacks) {
         I.nkernel = d.nkernel;
-        MWG_TRY(stage_input(d.kernel_index, (size_t)ng, d.mem, t_kidx, &kidx, s));
         MWG_TRY(stage_input(d.kernel_support, (size_t)d.nkernel, d.mem, t_ksup, &ksup, s));
         MWG_TRY(I.arena.alloc(&p, 8 * (size_t)d.kernel_elems));
         I.kstack = (float2 *)p;
@@ -572,12 +603,18 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         MWG_HIP(hipMemcpyAsync(I.ksup, d.kernel_support, 4 * (size_t)d.nkernel,
                                d.mem == MW_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
         std::vector<int32_t> hsup(d.nkernel);
+        std::vector<int64_t> hoff(d.nkernel);
         MWG_HIP(hipMemcpyAsync(hsup.data(), I.ksup, 4 * (size_t)d.nkernel, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipMemcpyAsync(hoff.data(), I.koff, 8 * (size_t)d.nkernel, hipMemcpyDeviceToHost, s));
         MWG_HIP(hipStreamSynchronize(s));
         I.max_support = 0;
-        for (int v : hsup) {
+        for (int k = 0; k < d.nkernel; k++) {
+            const int v = hsup[k];
             if (v < 1 || v > 63 || v % 2 == 0)
                 return make_error(MW_ERR_INVALID_ARG, "kernel support %d must be odd in [1, 63]", v);
+            const int64_t need = (int64_t)I.O * I.O * v * v;
+            if (hoff[k] < 0 || hoff[k] + need > d.kernel_elems)
+                return make_error(MW_ERR_INVALID_ARG, "kernel %d lies outside kernel_stack", k);
             I.max_support = std::max(I.max_support, v);
         }
     }

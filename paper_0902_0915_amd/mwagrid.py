@@ -273,6 +273,28 @@ class Plan:
             raise ValueError("pass a list with one entry per instance")
         return [x]
 
+    def _ngroups(self, i):
+        sp = self.specs[i]
+        return np.asarray(sp.uvw).shape[0] * np.asarray(sp.freq).shape[0]
+
+    def _check_shape(self, t, shape, what):
+        if t is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def _check_vis(self, lst, what):
+        for i, t in enumerate(lst):
+            self._check_shape(t, (self._ngroups(i), self.specs[i].npol), what)
+
+    def _check_grid(self, lst, what):
+        for i, t in enumerate(lst):
+            sp = self.specs[i]
+            self._check_shape(t, (sp.npol, sp.ny, sp.nx), what)
+
+    def _check_gains(self, lst):
+        for i, t in enumerate(lst):
+            if self.specs[i].nant > 0:  # an instance without antennas is refused by the library
+                self._check_shape(t, (self.specs[i].nant,), "gains")
+
     def new_grids(self):
         import torch
         return [torch.empty((sp.npol, sp.ny, sp.nx), dtype=torch.complex64, device=self.device)
@@ -282,6 +304,9 @@ class Plan:
         import torch
         vis_l, gains_l = self._as_list(vis), self._as_list(gains)
         outs = self._as_list(out) if out is not None else self.new_grids()
+        self._check_vis(vis_l, "vis")
+        self._check_grid(outs, "grid")
+        self._check_gains(gains_l)
         vp, _k1 = _ptr_array([_dev_ptr(v, torch.complex64, "vis") for v in vis_l])
         gp, _k2 = _ptr_array([_dev_ptr(g, torch.complex64, "gains") for g in gains_l])
         op, _k3 = _ptr_array([_dev_ptr(o, torch.complex64, "grid") for o in outs])
@@ -302,6 +327,10 @@ class Plan:
             outs = self._as_list(out)
         gg = [torch.empty(sp.nant, dtype=torch.complex64, device=self.device) if want_grad_gains
               else None for sp in self.specs]
+        self._check_grid(g_l, "grid")
+        self._check_vis(outs, "vis_out")
+        self._check_vis(vin_l, "vis_in")
+        self._check_gains(gains_l)
         gp, _k1 = _ptr_array([_dev_ptr(x, torch.complex64, "grid") for x in g_l])
         ga, _k2 = _ptr_array([_dev_ptr(x, torch.complex64, "gains") for x in gains_l])
         vi, _k3 = _ptr_array([_dev_ptr(x, torch.complex64, "vis_in") for x in vin_l])
@@ -319,6 +348,8 @@ class Plan:
         import torch
         x_l = self._as_list(x)
         outs = self._as_list(out) if out is not None else [torch.empty_like(t) for t in x_l]
+        self._check_grid(x_l, "in")
+        self._check_grid(outs, "out")
         ip, _k1 = _ptr_array([_dev_ptr(t, torch.complex64, "in") for t in x_l])
         op, _k2 = _ptr_array([_dev_ptr(t, torch.complex64, "out") for t in outs])
         _check(_lib.mw_image(self.handle, ip, op, int(direction), 1 if correct else 0,
