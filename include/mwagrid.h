@@ -92,12 +92,15 @@ typedef struct {
 
 /* Optional launch choices. Zero fields mean "choose automatically". */
 typedef struct {
-    int32_t tile;       /* uv tile edge in cells: 16, 32 or 64 */
+    int32_t tile;       /* uv tile edge in cells: 8, 16, 32 or 64 (8 needs W <= 15) */
     int32_t split;      /* max groups per work item (heavy tiles are split), >= 64 */
     int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 */
     int32_t order;      /* 1 = groups sorted by cell within a tile, 2 = input order */
-    int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes (npol 4), 3 = scatter */
-    int32_t flush;      /* 1 = atomic tile flush, 2 = deterministic two-pass merge */
+    int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes, 3 = scatter,
+                           4 = column lanes with a private tile per wavefront */
+    int32_t flush;      /* 1 = atomic adds of each finished tile into the zeroed grid,
+                           2 = tiles to a scratch buffer, then a merge pass writes the grid
+                           (with variant 4 the result is then bit-reproducible) */
     int32_t autotune;   /* 1 = time candidate launches on this plan's data and keep the best */
 } mw_tuning;
 
@@ -127,7 +130,7 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst,
  * vis[i]: device complex64 [ngroups][npol]. gains: NULL, or gains[i] NULL or device
  * complex64 [nant]. grid[i]: device complex64 [npol][ny][nx]. accumulate = 0 overwrites the
  * grid (zeroing is part of the call); 1 adds to it. FP32 accumulation; the summation order
- * is not fixed unless the deterministic flush was chosen.
+ * is fixed (bit-reproducible results) only with variant 4 and flush 2.
  * Errors: MW_ERR_INVALID_ARG (null plan/arrays), MW_ERR_STATE (gains for an instance planned
  * without antennas), MW_ERR_HIP (launch failure).
  */

@@ -26,6 +26,8 @@
 namespace mwg {
 
 size_t taplanes_lds(int npol, int T, int W, int O, int waves);
+size_t collanes_lds(int npol, int T, int W, int O, int waves);
+size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
 
 namespace {
@@ -45,14 +47,17 @@ __global__ void k_fill_zero1(float *p, int64_t n) {
 
 struct GridArgs {
     const float2 *vis;
-    const uint32_t *perm, *spos, *sant;
+    const uint32_t *perm, *spos, *sant, *scode;
     const float *sw;
     const float2 *gains;
     const WorkItem *work;
-    const float *taps2d, *tab;
+    const float *taps2d, *tab, *tab8;
     float2 *grid;
     float *partial;  // flush 2
     int nx, ny, T, ntx, W, O, str, plane;
+    // The tap table with rows padded to 8 floats, carried in the kernel arguments (constant
+    // memory): a wave-uniform row is then a single scalar load.
+    float tapk[16 * 8];
 };
 
 // LDS layout of a tile: 2*NPOL planes (re, im of each polarisation), each R rows of STR
@@ -64,6 +69,13 @@ __host__ __device__ inline int tile_stride(int R, int W) {
     return s;
 }
 __host__ __device__ inline int tile_plane(int R, int STR) { return (R * STR + 3) & ~3; }
+// Variant 2 puts the 2*npol component planes side by side in one lane set, so the plane
+// stride is also congruent to W (mod 32).
+__host__ __device__ inline int tile_plane2(int R, int STR, int W) {
+    int p = R * STR;
+    while ((p - W) % 32 != 0) p++;
+    return p;
+}
 
 // Multiply a group's visibilities by w * g1 * conj(g2) (when given).
 template <int NPOL>
@@ -231,6 +243,271 @@ __global__ __launch_bounds__(1024) void k_grid_taplanes(GridArgs a, int flush) {
     flush_tile<NPOL>(a, tile, flush, tx0, ty0, h, R, STR, PL);
 }
 
+
+// Variant 2 ("column lanes", 3 <= W <= 7): lane = (row group sg, component c, column t) with
+// c over the 2*NPOL real components of the visibility and NSG = 8/(2*NPOL) row groups, so
+// 8*W <= 64 lanes are active (56 for W = 7). A lane forms a = T[px][t] * V_c once per group
+// and adds T[py][s] * a into one register accumulator per footprint row s it owns
+// (s = sg, sg + NSG, ...). Each group costs the lane two 4-byte LDS reads (V_c and the
+// column tap); with NSG = 1 the row taps are wave-uniform scalar loads, otherwise LDS reads.
+// As in variant 1 the accumulators go to the LDS tile only when the centre cell changes.
+template <int NPOL, int W>
+__global__ __launch_bounds__(1024) void k_grid_collanes(GridArgs a, int flush) {
+    constexpr int NC = 2 * NPOL;        // real components per group
+    constexpr int NSG = 8 / NC;         // row groups
+    constexpr int NR = (W + NSG - 1) / NSG; // rows per lane
+    extern __shared__ __align__(16) float smem[];
+    const int nthreads = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = nthreads >> 6;
+    const WorkItem wk = a.work[blockIdx.x];
+    const int T = a.T, h = (W - 1) / 2, R = T + W - 1, STR = a.str, PL = a.plane;
+    const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
+    const int ntab = a.O * 8;           // tap rows padded to 8 floats
+    float *tile = smem;
+    float *ltab = smem + NC * PL;
+    float *sv = ltab + ntab + wave * 64 * NC;
+
+    for (int i = tid; i < NC * PL; i += nthreads) tile[i] = 0.0f;
+    for (int i = tid; i < ntab; i += nthreads) ltab[i] = a.tab8[i];
+    __syncthreads();
+
+    const int n = wk.end - wk.begin;
+    const int wb = wk.begin + (int)((int64_t)n * wave / nwaves);
+    const int we = wk.begin + (int)((int64_t)n * (wave + 1) / nwaves);
+    const int t = lane % W;
+    const int c = (lane / W) % NC;
+    const int sg = lane / (W * NC);
+    const bool active = lane < W * NC * NSG;
+    const int loff = active ? c * PL + sg * STR + t : 0;
+    const float *vl = sv + c;          // this lane's component of staged group j: vl[j * NC]
+    const float *txl = ltab + t;       // column tap: txl[px * 8]
+    float acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; k++) acc[k] = 0.0f;
+    int cur = -1;
+
+    uint32_t gA = (wb + lane < we) ? a.perm[wb + lane] : 0u;
+    uint32_t gB = (wb + 64 + lane < we) ? a.perm[wb + 64 + lane] : 0u;
+    float2 vn[NPOL];
+    if (wb + lane < we) fetch_group<NPOL>(a, wb + lane, gA, vn);
+
+    for (int base = wb; base < we; base += 64) {
+        const int cnt = (we - base) < 64 ? (we - base) : 64;
+        if (lane < cnt) {
+            float *dst = sv + lane * NC;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                dst[2 * p] = vn[p].x;
+                dst[2 * p + 1] = vn[p].y;
+            }
+        }
+        if (base + 64 + lane < we) fetch_group<NPOL>(a, base + 64 + lane, gB, vn);
+        gB = (base + 128 + lane < we) ? a.perm[base + 128 + lane] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t *cb = a.scode + base;
+        for (int j0 = 0; j0 < cnt; j0 += 8) {
+            uint32_t qq[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) qq[u] = cb[j0 + u]; // uniform; array padded by 64
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (j0 + u < cnt) {
+                    const uint32_t q = qq[u];
+                    const int cell = (int)(q & 0xFFFFu);
+                    const int txo = (int)((q >> 16) & 0xFFu);
+                    const int tyo = (int)(q >> 24);
+                    if (cell != cur) {
+                        if (cur >= 0 && active) {
+#pragma unroll
+                            for (int k = 0; k < NR; k++)
+                                if (sg + NSG * k < W)
+                                    atomicAdd(&tile[cur + loff + NSG * k * STR], acc[k]);
+                        }
+#pragma unroll
+                        for (int k = 0; k < NR; k++) acc[k] = 0.0f;
+                        cur = cell;
+                    }
+                    const float va = vl[(j0 + u) * NC] * txl[txo];
+                    if constexpr (NSG == 1) {
+                        // one 32-byte scalar load of the padded row of row taps
+                        const float4 *tyr = (const float4 *)__builtin_assume_aligned(a.tab8 + tyo, 32);
+                        const float4 r0 = tyr[0], r1 = tyr[1];
+                        const float ty[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+                        for (int k = 0; k < NR; k++) acc[k] = fmaf(ty[k], va, acc[k]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < NR; k++) {
+                            const int sr = sg + NSG * k;
+                            const float ty = ltab[tyo + (sr < W ? sr : 0)];
+                            acc[k] = fmaf(ty, va, acc[k]);
+                        }
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (cur >= 0 && active) {
+#pragma unroll
+        for (int k = 0; k < NR; k++)
+            if (sg + NSG * k < W) atomicAdd(&tile[cur + loff + NSG * k * STR], acc[k]);
+    }
+    __syncthreads();
+    flush_tile<NPOL>(a, tile, flush, tx0, ty0, h, R, STR, PL);
+}
+
+
+// Variant 4 ("wave tiles", 3 <= W <= 7): the lane layout of variant 2, but every wavefront
+// owns one work item and a private haloed tile in LDS (small tiles, T = 8 or 16). With no
+// other wavefront touching its tile, the accumulator flush on a cell change is a plain
+// LDS read-add-write instead of an LDS float atomic (which costs ~40x more on this chip).
+// The finished tile goes to HBM by atomic adds (flush 1) or into the work item's slice of
+// the partial buffer, summed by the merge pass (flush 2).
+// Adds a lane's row accumulators into its wave-private LDS tile: all reads are issued
+// before any write (the rows are distinct addresses), so the flush costs one LDS round trip.
+template <int NR, int NSG, int W>
+__device__ inline void wave_tile_add(float *p, int STR, int sg, const float (&acc)[NR]) {
+    float old[NR];
+#pragma unroll
+    for (int k = 0; k < NR; k++) old[k] = (sg + NSG * k < W) ? p[NSG * k * STR] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < NR; k++)
+        if (sg + NSG * k < W) p[NSG * k * STR] = old[k] + acc[k];
+}
+
+template <int NPOL, int W>
+__global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, int nwork) {
+    constexpr int NC = 2 * NPOL;
+    constexpr int NSG = 8 / NC;
+    constexpr int NR = (W + NSG - 1) / NSG;
+    extern __shared__ __align__(16) float smem[];
+    const int nthreads = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = nthreads >> 6;
+    const int ntab = a.O * 8;
+    float *ltab = smem;
+    for (int i = tid; i < ntab; i += nthreads) ltab[i] = a.tab8[i];
+    __syncthreads();
+    const int widx = blockIdx.x * nwaves + wave;
+    if (widx >= nwork) return;
+    const int T = a.T, h = (W - 1) / 2, R = T + W - 1, STR = a.str, PL = a.plane;
+    const int per_wave = NC * PL + 64 * NC;
+    float *tile = smem + ntab + wave * per_wave;
+    float *sv = tile + NC * PL;
+    const WorkItem wk = a.work[widx];
+    const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
+    for (int i = lane; i < NC * PL; i += 64) tile[i] = 0.0f;
+
+    const int wb = wk.begin, we = wk.end;
+    const int t = lane % W;
+    const int c = (lane / W) % NC;
+    const int sg = lane / (W * NC);
+    const bool active = lane < W * NC * NSG;
+    const int loff = active ? c * PL + sg * STR + t : 0;
+    const float *vl = sv + c;
+    const float *txl = ltab + t;
+    float acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; k++) acc[k] = 0.0f;
+    int cur = -1;
+
+    // Software pipeline over batches of 64 groups. Lane j holds group j's code in a VGPR
+    // (read into a scalar register per group with v_readlane) and stages its visibilities
+    // in LDS; the next batch's codes and visibilities and the permutation two batches ahead
+    // are in flight while a batch is accumulated.
+    uint32_t gA = (wb + lane < we) ? a.perm[wb + lane] : 0u;
+    uint32_t gB = (wb + 64 + lane < we) ? a.perm[wb + 64 + lane] : 0u;
+    uint32_t qn = (wb + lane < we) ? a.scode[wb + lane] : 0u;
+    float2 vn[NPOL];
+    if (wb + lane < we) fetch_group<NPOL>(a, wb + lane, gA, vn);
+
+    for (int base = wb; base < we; base += 64) {
+        const int cnt = (we - base) < 64 ? (we - base) : 64;
+        if (lane < cnt) {
+            float *dst = sv + lane * NC;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                dst[2 * p] = vn[p].x;
+                dst[2 * p + 1] = vn[p].y;
+            }
+        }
+        const uint32_t qcur = qn;
+        if (base + 64 + lane < we) {
+            fetch_group<NPOL>(a, base + 64 + lane, gB, vn);
+            qn = a.scode[base + 64 + lane];
+        }
+        gB = (base + 128 + lane < we) ? a.perm[base + 128 + lane] : 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int j0 = 0; j0 < cnt; j0 += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if (j0 + u < cnt) {
+                    const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)qcur, j0 + u);
+                    const int cell = (int)(q & 0xFFFFu);
+                    const int txo = (int)((q >> 16) & 0xFFu);
+                    const int tyo = (int)(q >> 24);
+                    if (cell != cur) {
+                        if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
+#pragma unroll
+                        for (int k = 0; k < NR; k++) acc[k] = 0.0f;
+                        cur = cell;
+                    }
+                    const float va = vl[(j0 + u) * NC] * txl[txo];
+                    if constexpr (NSG == 1) {
+                        const float *tyr = a.tapk + tyo;
+#pragma unroll
+                        for (int k = 0; k < NR; k++) acc[k] = fmaf(tyr[k], va, acc[k]);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < NR; k++) {
+                            const int sr = sg + NSG * k;
+                            acc[k] = fmaf(ltab[tyo + (sr < W ? sr : 0)], va, acc[k]);
+                        }
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // this wave's tile to HBM
+    if (flush == 1) {
+        for (int idx = lane; idx < R * R; idx += 64) {
+            const int r = idx / R, cc = idx - r * R;
+            const int gy = ty0 - h + r, gx = tx0 - h + cc;
+            if (gy < 0 || gy >= a.ny || gx < 0 || gx >= a.nx) continue;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                const float re = tile[(2 * p) * PL + r * STR + cc];
+                const float im = tile[(2 * p + 1) * PL + r * STR + cc];
+                float *dst = (float *)(a.grid + ((int64_t)p * a.ny + gy) * a.nx + gx);
+                if (re != 0.0f) atomicAdd(dst, re);
+                if (im != 0.0f) atomicAdd(dst + 1, im);
+            }
+        }
+    } else {
+        float *out = a.partial + (int64_t)widx * NC * R * R;
+        for (int idx = lane; idx < R * R; idx += 64) {
+            const int r = idx / R, cc = idx - r * R;
+#pragma unroll
+            for (int q = 0; q < NC; q++) out[(int64_t)q * R * R + idx] = tile[q * PL + r * STR + cc];
+        }
+    }
+}
+
 template <int NPOL>
 __global__ __launch_bounds__(1024) void k_grid_scatter(GridArgs a, int flush) {
     extern __shared__ __align__(16) float smem[];
@@ -317,8 +594,8 @@ template <int NPOL>
 Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s) {
     const Launch &L = I.L;
     const int R = L.tile + I.W - 1;
-    a.str = tile_stride(R, I.W);
-    a.plane = tile_plane(R, a.str);
+    a.str = L.variant == 4 ? R : tile_stride(R, I.W);
+    a.plane = (L.variant == 2 || L.variant == 4) ? tile_plane2(R, a.str, I.W) : tile_plane(R, a.str);
     const int flush = L.flush;
     const size_t need = sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * NPOL * R * R;
     if (flush == 2 && I.partial_bytes < need) {
@@ -335,6 +612,26 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
             const size_t lds = taplanes_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
             hipLaunchKernelGGL(k_grid_taplanes<NPOL>, dim3(I.nwork), dim3(64 * L.wg_waves), lds, s, a, flush);
+        } else if (L.variant == 2) {
+            const size_t lds = collanes_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
+            if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
+            const dim3 g(I.nwork), b(64 * L.wg_waves);
+            switch (I.W) {
+            case 3: hipLaunchKernelGGL((k_grid_collanes<NPOL, 3>), g, b, lds, s, a, flush); break;
+            case 5: hipLaunchKernelGGL((k_grid_collanes<NPOL, 5>), g, b, lds, s, a, flush); break;
+            case 7: hipLaunchKernelGGL((k_grid_collanes<NPOL, 7>), g, b, lds, s, a, flush); break;
+            default: return make_error(MW_ERR_UNSUPPORTED, "variant 2 needs W in {3, 5, 7}");
+            }
+        } else if (L.variant == 4) {
+            const size_t lds = wavetiles_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
+            if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
+            const dim3 g((I.nwork + L.wg_waves - 1) / L.wg_waves), b(64 * L.wg_waves);
+            switch (I.W) {
+            case 3: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 3>), g, b, lds, s, a, flush, I.nwork); break;
+            case 5: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 5>), g, b, lds, s, a, flush, I.nwork); break;
+            case 7: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 7>), g, b, lds, s, a, flush, I.nwork); break;
+            default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
+            }
         } else {
             const size_t lds = scatter_lds(NPOL, L.tile, I.W, I.O);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
@@ -357,6 +654,16 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
 size_t taplanes_lds(int npol, int T, int W, int O, int waves) {
     const int R = T + W - 1, STR = tile_stride(R, W), PL = tile_plane(R, STR);
     return 4 * ((size_t)2 * npol * PL + (size_t)O * O * 64) + (size_t)waves * 64 * (8 * npol);
+}
+
+size_t collanes_lds(int npol, int T, int W, int O, int waves) {
+    const int R = T + W - 1, STR = tile_stride(R, W), PL = tile_plane2(R, STR, W);
+    return 4 * ((size_t)2 * npol * PL + (size_t)O * 8) + (size_t)waves * 64 * 8 * npol;
+}
+
+size_t wavetiles_lds(int npol, int T, int W, int O, int waves) {
+    const int R = T + W - 1, PL = tile_plane2(R, R, W);
+    return 4 * ((size_t)O * 8 + (size_t)waves * (2 * npol * PL + 64 * 2 * npol));
 }
 
 size_t scatter_lds(int npol, int T, int W, int O) {
@@ -385,13 +692,19 @@ Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *
     a.vis = vis;
     a.perm = I.perm;
     a.spos = I.spos;
+    a.scode = I.scode;
     a.sant = I.sant;
     a.sw = I.sw;
     a.gains = gains;
     a.work = I.work;
     a.taps2d = I.taps2d;
     a.tab = I.tab;
+    a.tab8 = I.tab8;
     a.grid = grid;
+    for (int i = 0; i < 16 * 8; i++) a.tapk[i] = 0.0f;
+    if (!I.stacks && I.W <= 8)
+        for (int r = 0; r < I.O; r++)
+            for (int t = 0; t < I.W; t++) a.tapk[r * 8 + t] = I.h_tab[(size_t)r * I.W + t];
     a.nx = I.nx;
     a.ny = I.ny;
     a.T = I.L.tile;

@@ -87,13 +87,18 @@ struct Instance {
     uint32_t *sant = nullptr;     // [nkept] ant1 | ant2 << 16, sorted (or null)
     uint32_t *skid = nullptr;     // [nkept] kernel id, sorted (stacks)
     uint32_t *dropped = nullptr;  // [ngroups - nkept] original indices of dropped groups
+    uint32_t *scode = nullptr;    // [nkept + 64] per sorted group: LDS cell offset | px*W << 16 | py*W << 24
+    float *w_orig = nullptr;      // [ngroups] weights in input order (or null)
+    uint32_t *ant_orig = nullptr; // [nrow] ant1 | ant2 << 16 (or null)
+    int32_t *kidx_orig = nullptr; // [ngroups] kernel index (stacks)
     WorkItem *work = nullptr;     // [nwork]
     int32_t *tile_work = nullptr; // [ntiles + 1] CSR: work items of each tile (merge flush)
     int32_t *work_ids = nullptr;  // [nwork] work item ids grouped by tile
     float *partial = nullptr;     // merge flush scratch: [nwork][2*npol][R*R]
     size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)
-    float *tab = nullptr;         // [O][W]
+    float *tab = nullptr;         // [O][W] + 8 floats of padding
+    float *tab8 = nullptr;        // [O][8]: rows padded to 8 floats (W <= 7), 32-byte aligned
     float *corrx = nullptr, *corry = nullptr;
     float2 *kstack = nullptr;     // stacks: complex taps
     int64_t *koff = nullptr;

@@ -312,19 +312,35 @@ __global__ void k_tile_bounds(const uint32_t *skeys, int64_t nkept, int cellbits
 }
 
 __global__ void k_gather(const uint32_t *perm, int64_t nkept, int nchan, const uint32_t *pos,
-                         const float *weights, const int32_t *ant1, const int32_t *ant2,
-                         const int32_t *kidx, uint32_t *spos, float *sw, uint32_t *sant,
-                         uint32_t *skid) {
+                         const float *weights, const uint32_t *ants, const int32_t *kidx,
+                         uint32_t *spos, float *sw, uint32_t *sant, uint32_t *skid) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nkept) return;
     const uint32_t g = perm[i];
     spos[i] = pos[g];
     if (sw) sw[i] = weights[g];
-    if (sant) {
-        const int64_t r = (int64_t)g / nchan;
-        sant[i] = (uint32_t)ant1[r] | ((uint32_t)ant2[r] << 16);
-    }
+    if (sant) sant[i] = ants[(int64_t)g / nchan];
     if (skid) skid[i] = (uint32_t)kidx[g];
+}
+
+// Per sorted group, the gridder's precomputed addressing: the footprint origin inside the
+// haloed LDS tile (row stride STR) and the offsets of its two phase rows in the tap table
+// with rows padded to 8 floats.
+__global__ void k_codes(const uint32_t *spos, int64_t nkept, int tb, int STR, int W, int O,
+                        uint32_t *code) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nkept) return;
+    const uint32_t p = spos[i];
+    const uint32_t mask = (1u << tb) - 1u;
+    const uint32_t cx = p & 0xFFFu, cy = (p >> 12) & 0xFFFu;
+    const uint32_t px = (p >> 24) & 0xFu, py = p >> 28;
+    const uint32_t cell = (cy & mask) * (uint32_t)STR + (cx & mask);
+    code[i] = cell | ((px * 8u) << 16) | ((py * 8u) << 24);
+}
+
+__global__ void k_pack_ants(const int32_t *a1, const int32_t *a2, int64_t nrow, uint32_t *out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrow) out[r] = (uint32_t)a1[r] | ((uint32_t)a2[r] << 16);
 }
 
 // Counts entries of an index array outside [0, limit).
@@ -380,6 +396,12 @@ Status launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32, dim3(grid1d(n)), dim3(kBlock), 0, s, p, n, v);
     MWG_HIP(hipGetLastError());
     return Status::Ok();
+}
+
+int tile_stride_host(int R, int W) {
+    int st = R;
+    while ((st - W) % 32 != 0) st++;
+    return st;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -477,33 +499,48 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     MWG_HIP(hipMemcpyAsync(I.tile_work, tw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
     if (!ids.empty())
         MWG_HIP(hipMemcpyAsync(I.work_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
+    // Sorted per-group arrays follow the new permutation.
+    if (nk > 0) {
+        hipLaunchKernelGGL(k_gather, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.perm, nk, I.nchan, I.pos,
+                           I.w_orig, I.ant_orig, I.kidx_orig, I.spos, I.sw, I.sant, I.skid);
+        MWG_HIP(hipGetLastError());
+        if (!I.stacks) {
+            const int R = L.tile + I.W - 1;
+            hipLaunchKernelGGL(k_codes, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.spos, nk, tb,
+                               L.variant == 4 ? R : tile_stride_host(R, I.W), I.W, I.O, I.scode);
+            MWG_HIP(hipGetLastError());
+        }
+    }
     MWG_HIP(hipStreamSynchronize(s));
     return Status::Ok();
 }
 
 size_t taplanes_lds(int npol, int T, int W, int O, int waves);
+size_t collanes_lds(int npol, int T, int W, int O, int waves);
+size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
 
 static Launch default_launch(const Instance &I) {
     Launch L;
-    // LDS tile (T + W - 1)^2 * 2 * npol floats must fit beside the tap table and staging.
-    const int W = I.stacks ? I.max_support : I.W;
+    L.split = 8192;
+    L.order = 1;
     if (I.stacks) {
         L.tile = 64;
         L.variant = 3;
-    } else if (I.npol >= 4) {
-        L.tile = 32;
-    } else if (I.npol == 2) {
-        L.tile = 32;
+        L.wg_waves = 8;
+        L.flush = 1;
+    } else if (I.W >= 3 && I.W <= 7) {
+        // private 8x8 tiles per wavefront, merge pass: no LDS float atomics, no global atomics
+        L.tile = 8;
+        L.variant = 4;
+        L.wg_waves = 8;
+        L.flush = 2;
     } else {
-        L.tile = 64;
+        L.tile = I.npol >= 2 ? 32 : 64;
+        L.variant = (I.W * I.W <= 64) ? 1 : 3;
+        L.wg_waves = 8;
+        L.flush = 1;
     }
-    (void)W;
-    L.split = 8192;
-    L.wg_waves = 8;
-    L.order = 1;
-    L.flush = 1;
-    if (!I.stacks) L.variant = (I.W * I.W <= 64) ? 1 : 3;
     return L;
 }
 
@@ -520,11 +557,14 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         if (t->flush) L.flush = t->flush;
     }
     if (!I.stacks) {
-        if (L.variant == 2) return make_error(MW_ERR_UNSUPPORTED, "gridder variant 2 is not built");
+        if ((L.variant == 2 || L.variant == 4) && (I.W > 7 || I.W < 3))
+            return make_error(MW_ERR_UNSUPPORTED, "variants 2 and 4 need 3 <= W <= 7 (W = %d)", I.W);
         if (L.variant == 1 && I.W * I.W > 64)
             return make_error(MW_ERR_UNSUPPORTED, "variant 1 needs W*W <= 64 (W = %d)", I.W);
-        const size_t lds = L.variant == 1 ? taplanes_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
-                                          : scatter_lds(I.npol, L.tile, I.W, I.O);
+        const size_t lds = L.variant == 1   ? taplanes_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
+                           : L.variant == 2 ? collanes_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
+                           : L.variant == 4 ? wavetiles_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
+                                            : scatter_lds(I.npol, L.tile, I.W, I.O);
         if (lds > 160 * 1024)
             return make_error(MW_ERR_UNSUPPORTED, "launch needs %zu B of LDS (tile %d, npol %d)", lds,
                               L.tile, I.npol);
@@ -653,16 +693,35 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     I.nflagged = (int64_t)hc[1];
     I.noutside = (int64_t)hc[2];
 
+    // Input-order copies the schedule gathers from (weights, packed antenna pairs, kernels).
+    if (I.has_weights) {
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(ng, 1)));
+        I.w_orig = (float *)p;
+        if (ng > 0) MWG_HIP(hipMemcpyAsync(I.w_orig, weights, 4 * ng, hipMemcpyDeviceToDevice, s));
+    }
+    if (I.has_ants) {
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(I.nrow, 1)));
+        I.ant_orig = (uint32_t *)p;
+        if (I.nrow > 0) {
+            hipLaunchKernelGGL(k_pack_ants, dim3(grid1d(I.nrow)), dim3(kBlock), 0, s, a1, a2, I.nrow,
+                               I.ant_orig);
+            MWG_HIP(hipGetLastError());
+        }
+    }
+    if (I.stacks) {
+        MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(ng, 1)));
+        I.kidx_orig = (int32_t *)p;
+        if (ng > 0) MWG_HIP(hipMemcpyAsync(I.kidx_orig, kidx, 4 * ng, hipMemcpyDeviceToDevice, s));
+    }
     // A2: sort + schedule (perm holds all ngroups: kept first, then dropped in input order)
     MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(ng, 1)));
     I.perm = (uint32_t *)p;
     I.dropped = I.perm + I.nkept;
-    Launch L;
-    MWG_TRY(resolve_launch(I, tuning, &L));
-    MWG_TRY(rebuild_schedule(I, L, s));
     const int64_t nk = I.nkept;
     MWG_TRY(I.arena.alloc(&p, 4 * ((size_t)nk + 64)));  // + 64: the gridder reads ahead
     I.spos = (uint32_t *)p;
+    MWG_TRY(I.arena.alloc(&p, 4 * ((size_t)nk + 64)));
+    I.scode = (uint32_t *)p;
     if (I.has_weights) {
         MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(nk, 1)));
         I.sw = (float *)p;
@@ -675,11 +734,9 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(nk, 1)));
         I.skid = (uint32_t *)p;
     }
-    if (nk > 0) {
-        hipLaunchKernelGGL(k_gather, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.perm, nk, I.nchan,
-                           I.pos, weights, a1, a2, kidx, I.spos, I.sw, I.sant, I.skid);
-        MWG_HIP(hipGetLastError());
-    }
+    Launch L;
+    MWG_TRY(resolve_launch(I, tuning, &L));
+    MWG_TRY(rebuild_schedule(I, L, s));
 
     // A3: kernel tables (built-in kernel) and correction vectors
     if (!I.stacks) {
@@ -696,9 +753,17 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         MWG_TRY(I.arena.alloc(&p, 4 * taps2d.size()));
         I.taps2d = (float *)p;
         MWG_HIP(hipMemcpyAsync(I.taps2d, taps2d.data(), 4 * taps2d.size(), hipMemcpyHostToDevice, s));
-        MWG_TRY(I.arena.alloc(&p, 4 * I.h_tab.size()));
+        std::vector<float> tabpad(I.h_tab);
+        tabpad.resize(I.h_tab.size() + 8, 0.0f);  // uniform 8-float row reads past the last row
+        MWG_TRY(I.arena.alloc(&p, 4 * tabpad.size()));
         I.tab = (float *)p;
-        MWG_HIP(hipMemcpyAsync(I.tab, I.h_tab.data(), 4 * I.h_tab.size(), hipMemcpyHostToDevice, s));
+        MWG_HIP(hipMemcpyAsync(I.tab, tabpad.data(), 4 * tabpad.size(), hipMemcpyHostToDevice, s));
+        std::vector<float> tab8((size_t)I.O * 8, 0.0f);
+        for (int r = 0; r < I.O; r++)
+            for (int t = 0; t < I.W && t < 8; t++) tab8[(size_t)r * 8 + t] = I.h_tab[(size_t)r * I.W + t];
+        MWG_TRY(I.arena.alloc(&p, 4 * tab8.size()));
+        I.tab8 = (float *)p;
+        MWG_HIP(hipMemcpyAsync(I.tab8, tab8.data(), 4 * tab8.size(), hipMemcpyHostToDevice, s));
         MWG_TRY(I.arena.alloc(&p, 4 * (size_t)I.nx));
         I.corrx = (float *)p;
         MWG_HIP(hipMemcpyAsync(I.corrx, I.h_corrx.data(), 4 * (size_t)I.nx, hipMemcpyHostToDevice, s));

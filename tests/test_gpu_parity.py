@@ -87,6 +87,8 @@ def test_kernel_tables_match_oracle(mw, W, O):
 
 TUNINGS = [
     None,
+    dict(variant=1),
+    dict(variant=1, tile=16, flush=2, order=2),
     dict(tile=16, wg_waves=4),
     dict(tile=32, wg_waves=16, split=512),
     dict(tile=16, order=2, split=300),
@@ -94,7 +96,20 @@ TUNINGS = [
     dict(variant=3, tile=16, flush=2),
     dict(flush=2, split=700),
     dict(flush=2, tile=16, wg_waves=16, order=2),
+    dict(variant=4, tile=8, wg_waves=16, flush=2),
+    dict(variant=4, tile=16, wg_waves=8, flush=1),
+    dict(variant=4, tile=8, wg_waves=4, flush=1, split=256, order=2),
 ]
+
+
+def test_wave_tiles_merge_is_bit_reproducible(mw, small_mwa):
+    wl = small_mwa
+    with _plan(mw, wl, tuning=dict(variant=4, tile=8, flush=2), with_ants=False) as plan:
+        v = to_dev(wl.vis)
+        a = to_host(plan.grid(v))
+        b = to_host(plan.grid(v))
+    assert np.array_equal(a, b)
+    assert nl2(a, oracle_grid(wl, wl.vis)) <= TOL
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: "default" if t is None else
@@ -109,8 +124,23 @@ def test_grid_parity_mwa_4pol(mw, small_mwa, tuning):
     assert nl2(got, ref) <= TOL, nl2(got, ref)
 
 
+@pytest.mark.parametrize("npol", [1, 2, 4])
+@pytest.mark.parametrize("W", [3, 5, 7])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_grid_parity_variants(mw, npol, W, variant):
+    wl = synth.mwa_scale(seed=2005 + W, nant=40, nchan=4, ntime=2, npol=npol, n=256, nsrc=10,
+                         W=W, O=8)
+    ref = oracle_grid(wl, wl.vis)
+    tile = 8 if variant == 4 else (64 if npol == 1 else 32)
+    with _plan(mw, wl, tuning=dict(variant=variant, tile=tile, split=500),
+               with_ants=False) as plan:
+        got = to_host(plan.grid(to_dev(wl.vis)))
+        assert plan.info(0)["variant"] == variant
+    assert nl2(got, ref) <= TOL, nl2(got, ref)
+
+
 @pytest.mark.parametrize("tuning", [None, dict(tile=64, wg_waves=4), dict(variant=3),
-                                    dict(flush=2)], ids=str)
+                                    dict(flush=2), dict(variant=1)], ids=str)
 def test_grid_parity_tiny_1pol(mw, tiny, tuning):
     ref = oracle_grid(tiny, tiny.vis)
     with _plan(mw, tiny, tuning=tuning) as plan:
