@@ -97,7 +97,8 @@ typedef struct {
     int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 */
     int32_t order;      /* 1 = groups sorted by cell within a tile, 2 = input order */
     int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes, 3 = scatter,
-                           4 = column lanes with a private tile per wavefront */
+                           4 = column lanes with a private tile per wavefront,
+                           5 = kernel stacks, gathered by output tile (chosen for stacks) */
     int32_t flush;      /* 1 = atomic adds of each finished tile into the zeroed grid,
                            2 = tiles to a scratch buffer, then a merge pass writes the grid
                            (with variant 4 the result is then bit-reproducible) */

@@ -73,7 +73,7 @@ mwg::Status validate_tuning(const mw_tuning &t) {
     if (t.wg_waves != 0 && t.wg_waves != 4 && t.wg_waves != 8 && t.wg_waves != 16)
         return make_error(MW_ERR_INVALID_ARG, "tuning.wg_waves must be 0, 4, 8 or 16");
     if (t.order < 0 || t.order > 2) return make_error(MW_ERR_INVALID_ARG, "tuning.order must be 0, 1 or 2");
-    if (t.variant < 0 || t.variant > 4) return make_error(MW_ERR_INVALID_ARG, "tuning.variant must be 0..4");
+    if (t.variant < 0 || t.variant > 5) return make_error(MW_ERR_INVALID_ARG, "tuning.variant must be 0..5");
     if (t.flush < 0 || t.flush > 2) return make_error(MW_ERR_INVALID_ARG, "tuning.flush must be 0, 1 or 2");
     return mwg::Status::Ok();
 }

@@ -167,6 +167,7 @@ Status launch_degrid_npol(Instance &I, DegridArgs &a, hipStream_t s) {
 
 Status launch_degrid(Instance &I, const float2 *grid, const float2 *gains, const float2 *vis_in,
                      float2 *vis_out, float2 *grad_gains, hipStream_t s) {
+    if (I.stacks) return launch_degrid_stack(I, grid, gains, vis_in, vis_out, grad_gains, s);
     DegridArgs a{};
     a.grid = grid;
     a.gains = gains;

@@ -688,6 +688,7 @@ Status launch_fill_zero(void *ptr, size_t nbytes, hipStream_t s) {
 
 Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *grid, int accumulate,
                    hipStream_t s) {
+    if (I.stacks) return launch_grid_stack(I, vis, gains, grid, accumulate, s);
     GridArgs a{};
     a.vis = vis;
     a.perm = I.perm;

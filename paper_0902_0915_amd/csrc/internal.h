@@ -101,6 +101,8 @@ struct Instance {
     float *tab8 = nullptr;        // [O][8]: rows padded to 8 floats (W <= 7), 32-byte aligned
     float *corrx = nullptr, *corry = nullptr;
     float2 *kstack = nullptr;     // stacks: complex taps
+    uint32_t *pairs = nullptr;    // stacks: candidate group of each (tile, group) pair, by tile
+    int64_t npairs = 0;
     int64_t *koff = nullptr;
     int32_t *ksup = nullptr;
     // host copies for export
@@ -123,6 +125,15 @@ void prolate_tables(int W, int O, int nx, int ny, std::vector<float> &table,
 // plan.hip
 Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *t, hipStream_t s);
 Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s);
+
+// stack.hip
+Status build_stack_schedule(Instance &I, const Launch &L, hipStream_t s);
+Status launch_grid_stack(Instance &I, const float2 *vis, const float2 *gains, float2 *grid,
+                         int accumulate, hipStream_t s);
+Status launch_degrid_stack(Instance &I, const float2 *grid, const float2 *gains,
+                           const float2 *vis_in, float2 *vis_out, float2 *grad_gains,
+                           hipStream_t s);
+size_t stack_lds(int npol, int T, int waves);
 
 // grid.hip
 Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *grid,

@@ -276,11 +276,12 @@ Status scan_exclusive(uint32_t *data, int64_t n, hipStream_t s) {
 // Sorts (keys, implicit index) by the low keybits bits; result in keys_out/vals_out.
 Status radix_sort(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                   int64_t n, int keybits, uint32_t **keys_out, uint32_t **vals_out,
-                  hipStream_t s) {
+                  hipStream_t s, const uint32_t *vals_init = nullptr) {
     const int nblocks = (int)((n + kSortChunk - 1) / kSortChunk);
     Tmp hist;
     MWG_TRY(hist.alloc(sizeof(uint32_t) * 256 * (size_t)std::max(nblocks, 1)));
-    uint32_t *kin = keys, *kout = keys_alt, *vin = nullptr, *vout = vals;
+    uint32_t *kin = keys, *kout = keys_alt, *vout = vals;
+    const uint32_t *vin = vals_init;
     const int passes = (keybits + 7) / 8;
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
@@ -297,7 +298,7 @@ Status radix_sort(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *
     }
     if (passes == 0) return make_error(MW_ERR_UNSUPPORTED, "empty sort key");
     *keys_out = kin;
-    *vals_out = vin;
+    *vals_out = const_cast<uint32_t *>(vin); // after a pass vin is vals or vals_alt
     MWG_HIP(hipStreamSynchronize(s));
     return Status::Ok();
 }
@@ -390,6 +391,15 @@ Status stage_input(const T *src, size_t count, int mem, Tmp &tmp, const T **dst,
 }
 
 } // namespace
+
+// Library-internal entry points of the sort and scan (used by the kernel-stack schedule).
+Status sort_pairs(uint32_t *keys, uint32_t *keys_alt, const uint32_t *vals_init, uint32_t *vals,
+                  uint32_t *vals_alt, int64_t n, int keybits, uint32_t **keys_out,
+                  uint32_t **vals_out, hipStream_t s) {
+    return radix_sort(keys, keys_alt, vals, vals_alt, n, keybits, keys_out, vals_out, s, vals_init);
+}
+
+Status exclusive_scan_u32(uint32_t *data, int64_t n, hipStream_t s) { return scan_exclusive(data, n, s); }
 
 Status launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return Status::Ok();
@@ -525,10 +535,12 @@ static Launch default_launch(const Instance &I) {
     L.split = 8192;
     L.order = 1;
     if (I.stacks) {
-        L.tile = 64;
-        L.variant = 3;
+        // gather by output tile, one private tile per wavefront
+        L.tile = I.npol >= 2 ? 16 : 32;
+        L.variant = 5;
         L.wg_waves = 8;
         L.flush = 1;
+        L.split = 4096;
     } else if (I.W >= 3 && I.W <= 7) {
         // private 8x8 tiles per wavefront, merge pass: no LDS float atomics, no global atomics
         L.tile = 8;
@@ -555,6 +567,14 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         if (t->order) L.order = t->order;
         if (t->variant) L.variant = t->variant;
         if (t->flush) L.flush = t->flush;
+    }
+    if (I.stacks) {
+        L.variant = 5;
+        const size_t lds = stack_lds(I.npol, L.tile, L.wg_waves);
+        if (lds > 160 * 1024)
+            return make_error(MW_ERR_UNSUPPORTED, "stack tiles need %zu B of LDS (tile %d, npol %d, %d waves)",
+                              lds, L.tile, I.npol, L.wg_waves);
+        if (L.tile < 8) return make_error(MW_ERR_UNSUPPORTED, "stack tiles must be >= 8");
     }
     if (!I.stacks) {
         if ((L.variant == 2 || L.variant == 4) && (I.W > 7 || I.W < 3))
@@ -737,6 +757,7 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     Launch L;
     MWG_TRY(resolve_launch(I, tuning, &L));
     MWG_TRY(rebuild_schedule(I, L, s));
+    if (I.stacks) MWG_TRY(build_stack_schedule(I, L, s));
 
     // A3: kernel tables (built-in kernel) and correction vectors
     if (!I.stacks) {

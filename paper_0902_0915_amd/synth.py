@@ -381,9 +381,11 @@ def kernel_stacks(O=4, n_agroups=4, a_support=15, n_wplanes=32, wmax=200.0, seed
             np.array(supports, dtype=np.int32), wc)
 
 
-def beam_w_stacks(seed=3001, nant=128, nchan=8, ntime=16, n=4096, O=4, nsrc=20, wmax=200.0):
+def beam_w_stacks(seed=3001, nant=128, nchan=8, ntime=16, n=4096, O=4, nsrc=20, wmax=200.0,
+                  n_agroups=4, n_wplanes=32, npol=1):
     """128 antennas, 8 channels, 16 times, 1 polarisation; each visibility selects the kernel
-    (A-group pair, w-plane) with A-group = antenna index mod 4 and the w-plane holding its w;
+    (A-group pair, w-plane) with A-group = antenna index mod n_agroups and the w-plane holding
+    its w;
     4096^2 grid, oversampling 4. The phase centre is tilted from the zenith so that the
     largest |w| over the observation is ``wmax`` wavelengths."""
     rng = np.random.default_rng(seed)
@@ -401,19 +403,20 @@ def beam_w_stacks(seed=3001, nant=128, nchan=8, ntime=16, n=4096, O=4, nsrc=20, 
         else:
             lo = mid
     uvw = uvw_tracks(enu, a1, a2, has, MWA_LATITUDE + lo)
-    stack, koff, ksup, wc = kernel_stacks(O=O, wmax=wmax, seed=seed)
+    stack, koff, ksup, wc = kernel_stacks(O=O, n_agroups=n_agroups, n_wplanes=n_wplanes,
+                                          wmax=wmax, seed=seed)
     n_wplanes = len(wc)
     step = 2.0 * wmax / n_wplanes
     ant1, ant2 = np.tile(a1, ntime), np.tile(a2, ntime)
     wl_lambda = uvw[:, 2][:, None] * freq[None, :] / C_LIGHT  # [nrow, nchan]
     wp = np.clip(np.floor((wl_lambda + wmax) / step), 0, n_wplanes - 1).astype(np.int64)
-    agrp = (4 * (ant1 % 4) + (ant2 % 4)).astype(np.int64)
+    agrp = (n_agroups * (ant1 % n_agroups) + (ant2 % n_agroups)).astype(np.int64)
     kidx = (agrp[:, None] * n_wplanes + wp).reshape(-1).astype(np.int32)
     # Cell size: leave room for the largest half support (22 cells) beyond the 80% rule.
     du = cell_size(uvw, freq, n)
     sky = sky_powerlaw_box(nsrc, rng, 0.3 / du, 0.5, 10.0)
-    vis = predict_numpy(uvw, freq, sky, npol=1, noise=0.1, rng=rng)
-    wl = Workload("beam_w_stacks", seed, n, n, du, du, uvw, freq, 1, 0, O, ant1, ant2, nant,
+    vis = predict_numpy(uvw, freq, sky, npol=npol, noise=0.1, rng=rng)
+    wl = Workload("beam_w_stacks", seed, n, n, du, du, uvw, freq, npol, 0, O, ant1, ant2, nant,
                   vis=vis, sky=sky, kernel_stack=stack, kernel_offset=koff,
                   kernel_support=ksup, kernel_index=kidx)
     wl.meta.update(nbl=len(a1), ntime=ntime, wcentres=wc)

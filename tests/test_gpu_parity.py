@@ -90,12 +90,12 @@ TUNINGS = [
     dict(variant=1),
     dict(variant=1, tile=16, flush=2, order=2),
     dict(tile=16, wg_waves=4),
-    dict(tile=32, wg_waves=16, split=512),
+    dict(variant=2, tile=32, wg_waves=16, split=512),
     dict(tile=16, order=2, split=300),
     dict(variant=3, tile=32),
     dict(variant=3, tile=16, flush=2),
     dict(flush=2, split=700),
-    dict(flush=2, tile=16, wg_waves=16, order=2),
+    dict(variant=2, flush=2, tile=16, wg_waves=16, order=2),
     dict(variant=4, tile=8, wg_waves=16, flush=2),
     dict(variant=4, tile=16, wg_waves=8, flush=1),
     dict(variant=4, tile=8, wg_waves=4, flush=1, split=256, order=2),
