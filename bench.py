@@ -1,17 +1,21 @@
 """Benchmark of the gridding + imaging hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
 
-Workload (synthetic, seeded): the MWA-scale configuration - 512 antennas (density ~ 1/r
-within 1.5 km), 130,816 baselines x 32 channels x 8 times x 4 polarisations =
+Headline workload (synthetic, seeded): the MWA-scale configuration - 512 antennas (density
+~ 1/r within 1.5 km), 130,816 baselines x 32 channels x 8 times x 4 polarisations =
 133,955,584 complex64 visibilities from 1000 power-law point sources; 2048^2 grid per
 polarisation; prolate kernel support 7, oversampling 8; FP32 accumulation.
 
-A step is one forward pass of the imaging hot path over the batch, with the plan (FP64
-positions, tile sort, work list, kernel tables) built once beforehand for these uvw:
-mw_grid (zeroing included) then mw_image (+1, with the convolution correction). The plan,
-the gridder kernel alone, and a forward+backward pass (adding the image adjoint and the
-degridder) are reported beside it. Prints one JSON line on stdout; progress goes to stderr.
+A step is one forward pass of the imaging hot path over the batch: mw_grid (the gridder
+and its merge pass, which writes every cell, so no zeroing pass) then mw_image (+1, with
+the convolution correction). The plan (FP64 positions, tile sort, work list, kernel tables)
+is built once beforehand for these uvw and timed separately. Reported beside the step:
+the gridder kernel alone (HIP events the library records around its own launch), a
+forward + backward pass (adding the image adjoint and the degridder), and the batched
+workload: 96 uneven single-polarisation jobs gridded and degridded by one multi-instance
+plan (persistent launch replayed from a hipGraph) against 96 single-instance plans called
+one after another. One JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -26,8 +30,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Mvis/s gridded (support 7, 2048² grid) + % HBM roofline; fwd+bwd vs plain"
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published (packed); see the design doc
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
+KERNEL_NAMES = {1: "k_grid_taplanes", 2: "k_grid_collanes", 3: "k_grid_scatter",
+                4: "k_grid_wavetiles", 5: "k_grid_stack"}
 
 
 def log(msg):
@@ -40,16 +46,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000,
                     help="visibility groups (of 4 pols) in the oracle's timed sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
-    ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--split", type=int, default=0)
-    ap.add_argument("--wg-waves", type=int, default=0)
-    ap.add_argument("--flush", type=int, default=0)
-    ap.add_argument("--order", type=int, default=0)
-    ap.add_argument("--variant", type=int, default=0)
+    for k in ("tile", "split", "wg-waves", "flush", "order", "variant", "schedule", "autotune"):
+        ap.add_argument(f"--{k}", type=int, default=0)
     return ap.parse_args()
 
 
@@ -74,7 +77,6 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design in DESIGN.md, not built.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     torch.cuda.set_device(0)
@@ -100,8 +102,8 @@ def main():
     log(f"generated {wl.ngroups} groups x {wl.npol} pols in {time.perf_counter() - t0:.1f} s")
 
     tuning = {k: v for k, v in dict(tile=args.tile, split=args.split, wg_waves=args.wg_waves,
-                                     flush=args.flush, order=args.order,
-                                     variant=args.variant).items() if v}
+                                     flush=args.flush, order=args.order, variant=args.variant,
+                                     schedule=args.schedule, autotune=args.autotune).items() if v}
     spec = mwagrid.InstanceSpec.from_workload(wl, with_ants=False)
     t0 = time.perf_counter()
     plan = mwagrid.Plan(spec, tuning=tuning or None)
@@ -119,9 +121,6 @@ def main():
         plan.grid(vis, out=grid)
         plan.image(grid, direction=1, correct=True, out=img)
 
-    def grid_kernel_only():
-        plan.grid(vis, out=grid, accumulate=True)  # the gridder launch alone (no zeroing)
-
     def fwd_bwd():
         plan.grid(vis, out=grid)
         plan.image(grid, direction=1, correct=True, out=img)
@@ -134,25 +133,43 @@ def main():
     log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
     ev_ms, wall_ms = timed(step, args.steps, stream)
     log(f"step: {ev_ms:.3f} ms (events), {wall_ms:.3f} ms (wall)")
-    kern_ms, _ = timed(grid_kernel_only, args.steps, stream)
-    log(f"gridder kernel alone: {kern_ms:.3f} ms")
     fb_ms, _ = timed(fwd_bwd, max(1, args.steps // 2), stream)
     log(f"forward + backward: {fb_ms:.3f} ms")
+    # dominant kernel: the library's events around its own gridder launch, on its stream
+    plan.set_timing(True)
+    kms, mms = [], []
+    for _ in range(args.steps):
+        plan.grid(vis, out=grid)
+        g, m = plan.kernel_ms(0)
+        kms.append(g)
+        mms.append(m)
+    plan.set_timing(False)
+    kern_ms = sum(kms) / len(kms)
+    merge_ms = sum(mms) / len(mms)
+    log(f"gridder kernel {kern_ms:.4f} ms, merge {merge_ms:.4f} ms (averages of {len(kms)})")
 
     nvis = info["nkept"] * wl.npol
     value = nvis / (wall_ms * 1e-3) / 1e6
-    # Gridder algorithmic traffic: every kept visibility read once (8 B per pol) and the
-    # grid written once (8 B per cell per pol); flops: 49 taps x npol x complex FMA (4 flop).
+    # Algorithmic traffic of the gridder: every kept visibility read once (8 B per pol) and
+    # the grid written once (8 B per cell per pol). Flops: 49 taps x npol x complex-by-real
+    # FMA (4 flop) per kept group.
     alg_bytes = info["nkept"] * wl.npol * 8 + wl.npol * wl.nx * wl.ny * 8
     alg_flop = info["nkept"] * wl.W * wl.W * wl.npol * 4
-    hbm_gbs = alg_bytes / (kern_ms * 1e-3) / 1e9
     tflops = alg_flop / (kern_ms * 1e-3) / 1e12
+    kname = f"{KERNEL_NAMES.get(info['variant'], 'k_grid')}<{wl.npol},{wl.W}>"
     roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": "k_grid_taplanes<4>",
-                "kernel_ms": round(kern_ms, 4), "alg_flop": alg_flop}
-    hbm = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "alg_bytes": alg_bytes}
+                "traffic": None, "kernel": kname, "kernel_ms": round(kern_ms, 4),
+                "alg_flop_per_launch": alg_flop}
+    step_gbs = alg_bytes / (wall_ms * 1e-3) / 1e9
+    grid_gbs = alg_bytes / ((kern_ms + merge_ms) * 1e-3) / 1e9
+    hbm = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "alg_bytes_per_grid": alg_bytes,
+           "gridding_achieved": round(grid_gbs, 1), "gridding_frac": round(grid_gbs / HBM_PEAK_GBS, 4),
+           "step_frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(mwagrid, synth, stream, max(3, args.steps // 4))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -167,25 +184,74 @@ def main():
                                " x 32 channels x 8 times x 4 pols, 1000 sources, 2048^2 grid,"
                                " W=7, O=8", "visibilities": nvis, "grid": [wl.npol, wl.ny, wl.nx],
                    "launch": {k: info[k] for k in ("tile", "split", "wg_waves", "order",
-                                                   "variant", "flush", "nwork")}},
+                                                   "variant", "flush", "schedule", "nwork")}},
         "roofline": roofline,
         "hbm_roofline": hbm,
-        "grid_only_mvis_s": round(nvis / (kern_ms * 1e-3) / 1e6, 1),
+        "grid_mvis_s": round(nvis / ((kern_ms + merge_ms) * 1e-3) / 1e6, 1),
+        "merge_ms": round(merge_ms, 4),
         "step_event_ms": round(ev_ms, 4),
         "plan_ms": round(plan_ms, 1),
         "fwd_bwd_ms": round(fb_ms, 4),
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()
 
 
+def bench_batched(mwagrid, synth, stream, steps):
+    """96 uneven jobs: one batched plan (persistent launch + graph replay) against 96
+    single-instance plans, forward (grid) + backward (degrid) each."""
+    import torch
+
+    t0 = time.perf_counter()
+    log("batched workload: generating 96 uneven jobs")
+    jobs = synth.batched_jobs(device="cuda")
+    torch.cuda.synchronize()
+    nvis = sum(int((j.flags == 0).sum()) for j in jobs)
+    log(f"batched workload: {nvis} kept visibilities in {time.perf_counter() - t0:.1f} s")
+    specs = [mwagrid.InstanceSpec.from_workload(j, with_ants=False) for j in jobs]
+    vis = [j.vis for j in jobs]
+    t0 = time.perf_counter()
+    bplan = mwagrid.Plan(specs)
+    torch.cuda.synchronize()
+    bplan_ms = (time.perf_counter() - t0) * 1e3
+    grids = bplan.new_grids()
+    vouts = [torch.empty_like(v) for v in vis]
+
+    def batched_step():
+        bplan.grid(vis, out=grids)
+        bplan.degrid(grids, out=vouts)
+
+    singles = [mwagrid.Plan(sp) for sp in specs]
+
+    def sequential_step():
+        for p, v, g, o in zip(singles, vis, grids, vouts):
+            p.grid(v, out=g)
+            p.degrid(g, out=o)
+
+    for _ in range(2):
+        batched_step()
+        sequential_step()
+    b_ms, _ = timed(batched_step, steps, stream)
+    s_ms, _ = timed(sequential_step, steps, stream)
+    log(f"batched fwd+bwd {b_ms:.3f} ms vs sequential {s_ms:.3f} ms")
+    for p in singles:
+        p.close()
+    bplan.close()
+    return {"workload": "96 jobs, kept visibilities logU[1e4, 2e6] after 5-30% flagging, "
+                        "grids {512..4096}^2, W=7, O=8, 1 pol",
+            "visibilities": nvis, "batched_fwd_bwd_ms": round(b_ms, 4),
+            "sequential_fwd_bwd_ms": round(s_ms, 4), "speedup": round(s_ms / b_ms, 3),
+            "batched_mvis_s": round(nvis / (b_ms * 1e-3) / 1e6, 1),
+            "sequential_mvis_s": round(nvis / (s_ms * 1e-3) / 1e6, 1),
+            "batched_plan_ms": round(bplan_ms, 1)}
+
+
 def cpu_baseline(wl, vis_dev, sample_groups):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload: positions,
     gridding of the first ``sample_groups`` groups (all host cores, row stripes) and the
     image with correction; scaled to Mvis/s."""
-    import numpy as np
-
     import oracle as orc
 
     ng = min(sample_groups, wl.ngroups)

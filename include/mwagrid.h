@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MW_ABI_VERSION 1
+#define MW_ABI_VERSION 2
 
 typedef enum {
     MW_OK = 0,
@@ -102,13 +102,20 @@ typedef struct {
     int32_t flush;      /* 1 = atomic adds of each finished tile into the zeroed grid,
                            2 = tiles to a scratch buffer, then a merge pass writes the grid
                            (with variant 4 the result is then bit-reproducible) */
-    int32_t autotune;   /* 1 = time candidate launches on this plan's data and keep the best */
+    int32_t autotune;   /* 1 = time candidate launches (tile, waves, split, schedule, flush)
+                           on this plan's own positions and keep the fastest; if the
+                           environment variable MW_TUNE_CACHE names a file, results are
+                           read from and appended to it, keyed by grid size, W, O, npol
+                           and the order of magnitude of the visibility count */
+    int32_t schedule;   /* work-item order: 1 = largest first, 2 = Z-order of tiles split into
+                           8 equal-work chunks, one per XCD (variant 4 only) */
 } mw_tuning;
 
 typedef struct {
     int64_t ngroups, nkept, nflagged, noutside;
     int32_t ntiles, nwork;        /* non-empty tiles and work items */
     int32_t tile, split, wg_waves, order, variant, flush; /* the launch actually chosen */
+    int32_t schedule;
     int64_t plan_bytes;           /* device memory owned by the plan for this instance */
 } mw_plan_stats;
 
@@ -182,6 +189,20 @@ mw_status mw_plan_positions(mw_plan plan, int32_t inst, int32_t *pos_host);
  */
 mw_status mw_plan_tables(mw_plan plan, int32_t inst, float *table_host, float *corr_x,
                          float *corr_y);
+
+/*
+ * Profiling of the library's own launches. With enable = 1, every later mw_grid call on the
+ * plan records HIP events on its stream around the gridder kernel and the merge pass of each
+ * instance (a few microseconds of overhead); enable = 0 stops it.
+ */
+mw_status mw_plan_set_timing(mw_plan plan, int32_t enable);
+
+/*
+ * Durations of the last timed mw_grid call of instance inst (waits for that call to
+ * finish): grid_ms = the gridder kernel, merge_ms = the merge pass (0 when the launch has
+ * none). Either pointer may be NULL. MW_ERR_STATE if no timed call was made.
+ */
+mw_status mw_plan_kernel_ms(mw_plan plan, int32_t inst, float *grid_ms, float *merge_ms);
 
 /* Release everything the plan owns (waits for its outstanding work). NULL is a no-op. */
 mw_status mw_plan_destroy(mw_plan plan);

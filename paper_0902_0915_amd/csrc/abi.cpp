@@ -75,6 +75,7 @@ mwg::Status validate_tuning(const mw_tuning &t) {
     if (t.order < 0 || t.order > 2) return make_error(MW_ERR_INVALID_ARG, "tuning.order must be 0, 1 or 2");
     if (t.variant < 0 || t.variant > 5) return make_error(MW_ERR_INVALID_ARG, "tuning.variant must be 0..5");
     if (t.flush < 0 || t.flush > 2) return make_error(MW_ERR_INVALID_ARG, "tuning.flush must be 0, 1 or 2");
+    if (t.schedule < 0 || t.schedule > 2) return make_error(MW_ERR_INVALID_ARG, "tuning.schedule must be 0, 1 or 2");
     return mwg::Status::Ok();
 }
 
@@ -94,6 +95,8 @@ void destroy_plan(mwg::Plan *P) {
     mwg::batch_release(*P);
     for (mwg::Instance *I : P->inst) {
         if (!I) continue;
+        for (hipEvent_t &e : I->tev)
+            if (e) (void)hipEventDestroy(e);
         mwg::image_release(*I);
         I->arena.release();
         delete I;
@@ -136,7 +139,6 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
             P->inst.push_back(I);
             mwg::Status s = mwg::build_instance(*I, inst[i], tuning, st);
             if (s.ok() && tuning && tuning->autotune) s = mwg::autotune(*I, st);
-            if (s.ok() && !I->stacks) s = mwg::image_prepare(*I);
             if (!s.ok()) {
                 destroy_plan(P);
                 return fail(s);
@@ -286,6 +288,7 @@ mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out) {
             out->order = I.L.order;
             out->variant = I.L.variant;
             out->flush = I.L.flush;
+            out->schedule = I.L.schedule;
         }
         return ok();
     } catch (...) {
@@ -338,6 +341,45 @@ mw_status mw_plan_tables(mw_plan plan, int32_t inst, float *table_host, float *c
         return ok();
     } catch (...) {
         return fail(MW_ERR_HIP, "unexpected exception in mw_plan_tables");
+    }
+}
+
+mw_status mw_plan_set_timing(mw_plan plan, int32_t enable) {
+    try {
+        mwg::Status s = check_plan(plan);
+        if (!s.ok()) return fail(s);
+        mwg::Plan *P = (mwg::Plan *)plan;
+        for (mwg::Instance *I : P->inst) {
+            if (enable)
+                for (hipEvent_t &e : I->tev)
+                    if (!e && hipEventCreate(&e) != hipSuccess) return fail(MW_ERR_HIP, "hipEventCreate failed");
+            I->timing = enable != 0;
+            I->timed = false;
+        }
+        return ok();
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_plan_set_timing");
+    }
+}
+
+mw_status mw_plan_kernel_ms(mw_plan plan, int32_t inst, float *grid_ms, float *merge_ms) {
+    try {
+        mwg::Status s = check_plan(plan);
+        if (!s.ok()) return fail(s);
+        mwg::Plan *P = (mwg::Plan *)plan;
+        if (inst < 0 || inst >= (int)P->inst.size()) return fail(MW_ERR_INVALID_ARG, "inst out of range");
+        mwg::Instance &I = *P->inst[inst];
+        if (!I.timed) return fail(MW_ERR_STATE, "no timed mw_grid call on this instance");
+        if (hipEventSynchronize(I.tev[2]) != hipSuccess) return fail(MW_ERR_HIP, "hipEventSynchronize failed");
+        float g = 0.f, m = 0.f;
+        if (hipEventElapsedTime(&g, I.tev[0], I.tev[1]) != hipSuccess ||
+            hipEventElapsedTime(&m, I.tev[1], I.tev[2]) != hipSuccess)
+            return fail(MW_ERR_HIP, "hipEventElapsedTime failed");
+        if (grid_ms) *grid_ms = g;
+        if (merge_ms) *merge_ms = m;
+        return ok();
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_plan_kernel_ms");
     }
 }
 

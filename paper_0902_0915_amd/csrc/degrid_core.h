@@ -1,0 +1,121 @@
+// Shared device code of the separable degridder, used by the single-instance kernel
+// (degrid.hip) and the batched kernel (batched.hip).
+#pragma once
+
+#include "internal.h"
+
+namespace mwg {
+
+struct DegridArgs {
+    const float2 *grid, *gains, *vis_in;
+    float2 *vis_out, *grad_gains;
+    const uint32_t *perm, *spos, *sant;
+    const float *sw;
+    const WorkItem *work;
+    const float *tab;
+    int nx, ny, T, ntx, W, O, nant, ant_in_lds;
+};
+
+// One workgroup grids-back one work item: stage its haloed grid tile in LDS, then one
+// thread per group gathers the footprint. smem is the workgroup's dynamic LDS.
+template <int NPOL>
+__device__ inline void degrid_item(const DegridArgs &a, const WorkItem wk, float *smem) {
+    const int nthreads = blockDim.x, tid = threadIdx.x;
+    const int T = a.T, W = a.W, h = (W - 1) / 2, R = T + W - 1;
+    const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
+    float2 *g = (float2 *)smem;                      // [NPOL][R][R]
+    float *tab = (float *)(g + (size_t)NPOL * R * R); // [O][W]
+    float2 *gacc = (float2 *)(tab + ((a.O * W + 1) & ~1)); // [nant] when in LDS
+    for (int idx = tid; idx < NPOL * R * R; idx += nthreads) {
+        const int p = idx / (R * R), rc = idx - p * R * R;
+        const int r = rc / R, c = rc - r * R;
+        const int gy = ty0 - h + r, gx = tx0 - h + c;
+        float2 v = make_float2(0.f, 0.f);
+        if (gy >= 0 && gy < a.ny && gx >= 0 && gx < a.nx) v = a.grid[((int64_t)p * a.ny + gy) * a.nx + gx];
+        g[idx] = v;
+    }
+    for (int i = tid; i < a.O * W; i += nthreads) tab[i] = a.tab[i];
+    const bool want_g = a.grad_gains != nullptr;
+    if (want_g && a.ant_in_lds)
+        for (int i = tid; i < a.nant; i += nthreads) gacc[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int64_t i = wk.begin + tid; i < wk.end; i += nthreads) {
+        const uint32_t pp = a.spos[i];
+        const int cx = (int)(pp & 0xFFFu), cy = (int)((pp >> 12) & 0xFFFu);
+        const int px = (int)((pp >> 24) & 0xFu), py = (int)(pp >> 28);
+        const int o = (cy - ty0) * R + (cx - tx0);
+        float2 acc[NPOL];
+#pragma unroll
+        for (int p = 0; p < NPOL; p++) acc[p] = make_float2(0.f, 0.f);
+        for (int sy = 0; sy < W; sy++) {
+            const float ty = tab[py * W + sy];
+            const float2 *row = g + o + sy * R;
+            for (int sx = 0; sx < W; sx++) {
+                const float tap = ty * tab[px * W + sx];
+#pragma unroll
+                for (int p = 0; p < NPOL; p++) {
+                    const float2 v = row[(size_t)p * R * R + sx];
+                    acc[p].x = fmaf(tap, v.x, acc[p].x);
+                    acc[p].y = fmaf(tap, v.y, acc[p].y);
+                }
+            }
+        }
+        const float w = a.sw ? a.sw[i] : 1.0f;
+#pragma unroll
+        for (int p = 0; p < NPOL; p++) {
+            acc[p].x *= w;
+            acc[p].y *= w;
+        }
+        const uint32_t gi = a.perm[i];
+        float2 out[NPOL];
+        if (a.gains) {
+            const uint32_t an = a.sant[i];
+            const int a1 = (int)(an & 0xFFFFu), a2 = (int)(an >> 16);
+            const float2 g1 = a.gains[a1], g2 = a.gains[a2];
+            // conj(g1) * g2
+            const float mr = g1.x * g2.x + g1.y * g2.y, mi = g1.x * g2.y - g1.y * g2.x;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++)
+                out[p] = make_float2(mr * acc[p].x - mi * acc[p].y, mr * acc[p].y + mi * acc[p].x);
+            if (want_g) {
+                float2 t1 = make_float2(0.f, 0.f), t2 = make_float2(0.f, 0.f);
+                const float2 *vin = a.vis_in + (int64_t)gi * NPOL;
+#pragma unroll
+                for (int p = 0; p < NPOL; p++) {
+                    const float2 V = vin[p], y = acc[p];
+                    // conj(V) * y and V * conj(y)
+                    const float cr = V.x * y.x + V.y * y.y, ci = V.x * y.y - V.y * y.x;
+                    t1.x += cr;
+                    t1.y += ci;
+                    t2.x += cr;
+                    t2.y -= ci;
+                }
+                // grad[a1] += g2 * t1 ; grad[a2] += g1 * t2
+                const float2 d1 = make_float2(g2.x * t1.x - g2.y * t1.y, g2.x * t1.y + g2.y * t1.x);
+                const float2 d2 = make_float2(g1.x * t2.x - g1.y * t2.y, g1.x * t2.y + g1.y * t2.x);
+                float2 *dst = a.ant_in_lds ? gacc : a.grad_gains;
+                atomicAdd(&dst[a1].x, d1.x);
+                atomicAdd(&dst[a1].y, d1.y);
+                atomicAdd(&dst[a2].x, d2.x);
+                atomicAdd(&dst[a2].y, d2.y);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) out[p] = acc[p];
+        }
+        float2 *dst = a.vis_out + (int64_t)gi * NPOL;
+#pragma unroll
+        for (int p = 0; p < NPOL; p++) dst[p] = out[p];
+    }
+    if (want_g && a.ant_in_lds) {
+        __syncthreads();
+        for (int i = tid; i < a.nant; i += nthreads) {
+            const float2 v = gacc[i];
+            if (v.x != 0.0f) atomicAdd(&a.grad_gains[i].x, v.x);
+            if (v.y != 0.0f) atomicAdd(&a.grad_gains[i].y, v.y);
+        }
+    }
+}
+
+
+} // namespace mwg

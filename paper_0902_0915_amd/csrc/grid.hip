@@ -20,6 +20,7 @@
 //             2 = plain stores of each tile into a per-work-item buffer and a merge pass
 //                 that sums the (at most nine) overlapping tiles of every cell.
 #include "internal.h"
+#include "gridder_core.h"
 
 #include <algorithm>
 
@@ -29,6 +30,7 @@ size_t taplanes_lds(int npol, int T, int W, int O, int waves);
 size_t collanes_lds(int npol, int T, int W, int O, int waves);
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
+Status ensure_partial(Instance &I, hipStream_t s);
 
 namespace {
 
@@ -58,6 +60,9 @@ struct GridArgs {
     // The tap table with rows padded to 8 floats, carried in the kernel arguments (constant
     // memory): a wave-uniform row is then a single scalar load.
     float tapk[16 * 8];
+    // schedule 2: logical workgroup ranges per XCD (hardware workgroup h runs on XCD h % 8)
+    int xcd_start[9];
+    int schedule;
 };
 
 // LDS layout of a tile: 2*NPOL planes (re, im of each polarisation), each R rows of STR
@@ -369,23 +374,9 @@ __global__ __launch_bounds__(1024) void k_grid_collanes(GridArgs a, int flush) {
 // LDS read-add-write instead of an LDS float atomic (which costs ~40x more on this chip).
 // The finished tile goes to HBM by atomic adds (flush 1) or into the work item's slice of
 // the partial buffer, summed by the merge pass (flush 2).
-// Adds a lane's row accumulators into its wave-private LDS tile: all reads are issued
-// before any write (the rows are distinct addresses), so the flush costs one LDS round trip.
-template <int NR, int NSG, int W>
-__device__ inline void wave_tile_add(float *p, int STR, int sg, const float (&acc)[NR]) {
-    float old[NR];
-#pragma unroll
-    for (int k = 0; k < NR; k++) old[k] = (sg + NSG * k < W) ? p[NSG * k * STR] : 0.0f;
-#pragma unroll
-    for (int k = 0; k < NR; k++)
-        if (sg + NSG * k < W) p[NSG * k * STR] = old[k] + acc[k];
-}
-
 template <int NPOL, int W>
 __global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, int nwork) {
     constexpr int NC = 2 * NPOL;
-    constexpr int NSG = 8 / NC;
-    constexpr int NR = (W + NSG - 1) / NSG;
     extern __shared__ __align__(16) float smem[];
     const int nthreads = blockDim.x, tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -394,118 +385,42 @@ __global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, 
     float *ltab = smem;
     for (int i = tid; i < ntab; i += nthreads) ltab[i] = a.tab8[i];
     __syncthreads();
-    const int widx = blockIdx.x * nwaves + wave;
+    int lb = blockIdx.x;
+    if (a.schedule == 2) {
+        const int x = blockIdx.x & 7;
+        lb = a.xcd_start[x] + (blockIdx.x >> 3);
+        if (lb >= a.xcd_start[x + 1]) return;
+    }
+    const int widx = lb * nwaves + wave;
     if (widx >= nwork) return;
-    const int T = a.T, h = (W - 1) / 2, R = T + W - 1, STR = a.str, PL = a.plane;
-    const int per_wave = NC * PL + 64 * NC;
-    float *tile = smem + ntab + wave * per_wave;
-    float *sv = tile + NC * PL;
+    const int R = a.T + W - 1;
+    const int per_wave = NC * a.plane + 64 * NC;
+    ItemCtx c;
+    c.tile = smem + ntab + wave * per_wave;
+    c.sv = c.tile + NC * a.plane;
+    for (int i = lane; i < NC * a.plane; i += 64) c.tile[i] = 0.0f;
     const WorkItem wk = a.work[widx];
-    const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
-    for (int i = lane; i < NC * PL; i += 64) tile[i] = 0.0f;
-
-    const int wb = wk.begin, we = wk.end;
-    const int t = lane % W;
-    const int c = (lane / W) % NC;
-    const int sg = lane / (W * NC);
-    const bool active = lane < W * NC * NSG;
-    const int loff = active ? c * PL + sg * STR + t : 0;
-    const float *vl = sv + c;
-    const float *txl = ltab + t;
-    float acc[NR];
-#pragma unroll
-    for (int k = 0; k < NR; k++) acc[k] = 0.0f;
-    int cur = -1;
-
-    // Software pipeline over batches of 64 groups. Lane j holds group j's code in a VGPR
-    // (read into a scalar register per group with v_readlane) and stages its visibilities
-    // in LDS; the next batch's codes and visibilities and the permutation two batches ahead
-    // are in flight while a batch is accumulated.
-    uint32_t gA = (wb + lane < we) ? a.perm[wb + lane] : 0u;
-    uint32_t gB = (wb + 64 + lane < we) ? a.perm[wb + 64 + lane] : 0u;
-    uint32_t qn = (wb + lane < we) ? a.scode[wb + lane] : 0u;
-    float2 vn[NPOL];
-    if (wb + lane < we) fetch_group<NPOL>(a, wb + lane, gA, vn);
-
-    for (int base = wb; base < we; base += 64) {
-        const int cnt = (we - base) < 64 ? (we - base) : 64;
-        if (lane < cnt) {
-            float *dst = sv + lane * NC;
-#pragma unroll
-            for (int p = 0; p < NPOL; p++) {
-                dst[2 * p] = vn[p].x;
-                dst[2 * p + 1] = vn[p].y;
-            }
-        }
-        const uint32_t qcur = qn;
-        if (base + 64 + lane < we) {
-            fetch_group<NPOL>(a, base + 64 + lane, gB, vn);
-            qn = a.scode[base + 64 + lane];
-        }
-        gB = (base + 128 + lane < we) ? a.perm[base + 128 + lane] : 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int j0 = 0; j0 < cnt; j0 += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                if (j0 + u < cnt) {
-                    const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)qcur, j0 + u);
-                    const int cell = (int)(q & 0xFFFFu);
-                    const int txo = (int)((q >> 16) & 0xFFu);
-                    const int tyo = (int)(q >> 24);
-                    if (cell != cur) {
-                        if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
-#pragma unroll
-                        for (int k = 0; k < NR; k++) acc[k] = 0.0f;
-                        cur = cell;
-                    }
-                    const float va = vl[(j0 + u) * NC] * txl[txo];
-                    if constexpr (NSG == 1) {
-                        const float *tyr = a.tapk + tyo;
-#pragma unroll
-                        for (int k = 0; k < NR; k++) acc[k] = fmaf(tyr[k], va, acc[k]);
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < NR; k++) {
-                            const int sr = sg + NSG * k;
-                            acc[k] = fmaf(ltab[tyo + (sr < W ? sr : 0)], va, acc[k]);
-                        }
-                    }
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // this wave's tile to HBM
-    if (flush == 1) {
-        for (int idx = lane; idx < R * R; idx += 64) {
-            const int r = idx / R, cc = idx - r * R;
-            const int gy = ty0 - h + r, gx = tx0 - h + cc;
-            if (gy < 0 || gy >= a.ny || gx < 0 || gx >= a.nx) continue;
-#pragma unroll
-            for (int p = 0; p < NPOL; p++) {
-                const float re = tile[(2 * p) * PL + r * STR + cc];
-                const float im = tile[(2 * p + 1) * PL + r * STR + cc];
-                float *dst = (float *)(a.grid + ((int64_t)p * a.ny + gy) * a.nx + gx);
-                if (re != 0.0f) atomicAdd(dst, re);
-                if (im != 0.0f) atomicAdd(dst + 1, im);
-            }
-        }
-    } else {
-        float *out = a.partial + (int64_t)widx * NC * R * R;
-        for (int idx = lane; idx < R * R; idx += 64) {
-            const int r = idx / R, cc = idx - r * R;
-#pragma unroll
-            for (int q = 0; q < NC; q++) out[(int64_t)q * R * R + idx] = tile[q * PL + r * STR + cc];
-        }
-    }
+    c.vis = a.vis;
+    c.gains = a.gains;
+    c.perm = a.perm;
+    c.scode = a.scode;
+    c.sant = a.sant;
+    c.sw = a.sw;
+    c.tapk = a.tapk;
+    c.ltab = ltab;
+    c.grid = a.grid;
+    c.partial = a.partial + (int64_t)widx * NC * R * R;
+    c.wb = wk.begin;
+    c.we = wk.end;
+    c.tx0 = (wk.tile % a.ntx) * a.T;
+    c.ty0 = (wk.tile / a.ntx) * a.T;
+    c.T = a.T;
+    c.STR = a.str;
+    c.PL = a.plane;
+    c.nx = a.nx;
+    c.ny = a.ny;
+    c.flush = flush;
+    wavetile_item<NPOL, W>(c, lane);
 }
 
 template <int NPOL>
@@ -554,40 +469,7 @@ __global__ void k_merge(float2 *grid, const float *partial, const int32_t *tile_
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= nx) return;
-    const int h = (W - 1) / 2, R = T + W - 1;
-    float acc[2 * NPOL];
-#pragma unroll
-    for (int q = 0; q < 2 * NPOL; q++) acc[q] = 0.0f;
-    const int txc = x / T, tyc = y / T;
-    for (int dy = -1; dy <= 1; dy++) {
-        const int tty = tyc + dy;
-        if (tty < 0 || tty >= nty) continue;
-        const int r = y - (tty * T - h);
-        if (r < 0 || r >= R) continue;
-        for (int dx = -1; dx <= 1; dx++) {
-            const int ttx = txc + dx;
-            if (ttx < 0 || ttx >= ntx) continue;
-            const int c = x - (ttx * T - h);
-            if (c < 0 || c >= R) continue;
-            const int t = tty * ntx + ttx;
-            for (int k = tile_work[t]; k < tile_work[t + 1]; k++) {
-                const float *src = partial + (int64_t)work_ids[k] * (2 * NPOL) * R * R + r * R + c;
-#pragma unroll
-                for (int q = 0; q < 2 * NPOL; q++) acc[q] += src[(int64_t)q * R * R];
-            }
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < NPOL; p++) {
-        float2 *dst = grid + ((int64_t)p * ny + y) * nx + x;
-        float2 v = make_float2(acc[2 * p], acc[2 * p + 1]);
-        if (accumulate) {
-            const float2 o = *dst;
-            v.x += o.x;
-            v.y += o.y;
-        }
-        *dst = v;
-    }
+    merge_cell<NPOL>(grid, partial, tile_work, work_ids, nx, ny, T, ntx, nty, W, accumulate, x, y);
 }
 
 template <int NPOL>
@@ -597,16 +479,11 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
     a.str = L.variant == 4 ? R : tile_stride(R, I.W);
     a.plane = (L.variant == 2 || L.variant == 4) ? tile_plane2(R, a.str, I.W) : tile_plane(R, a.str);
     const int flush = L.flush;
-    const size_t need = sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * NPOL * R * R;
-    if (flush == 2 && I.partial_bytes < need) {
-        void *p;
-        MWG_TRY(I.arena.alloc(&p, need));
-        I.partial = (float *)p;
-        I.partial_bytes = need;
-    }
+    if (flush == 2) MWG_TRY(ensure_partial(I, s));
     a.partial = I.partial;
     if (flush == 1 && !accumulate)
         MWG_TRY(launch_fill_zero(a.grid, sizeof(float2) * (size_t)NPOL * I.nx * I.ny, s));
+    if (I.timing) MWG_HIP(hipEventRecord(I.tev[0], s));
     if (I.nwork > 0) {
         if (L.variant == 1) {
             const size_t lds = taplanes_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
@@ -625,7 +502,10 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
         } else if (L.variant == 4) {
             const size_t lds = wavetiles_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
-            const dim3 g((I.nwork + L.wg_waves - 1) / L.wg_waves), b(64 * L.wg_waves);
+            const dim3 g(L.schedule == 2 ? 8 * I.xcd_wgs : (I.nwork + L.wg_waves - 1) / L.wg_waves),
+                b(64 * L.wg_waves);
+            a.schedule = L.schedule;
+            for (int x = 0; x < 9; x++) a.xcd_start[x] = I.xcd_start[x];
             switch (I.W) {
             case 3: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 3>), g, b, lds, s, a, flush, I.nwork); break;
             case 5: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 5>), g, b, lds, s, a, flush, I.nwork); break;
@@ -639,12 +519,17 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
         }
         MWG_HIP(hipGetLastError());
     }
+    if (I.timing) MWG_HIP(hipEventRecord(I.tev[1], s));
     if (flush == 2) {
         dim3 blk(256), grd((I.nx + 255) / 256, I.ny);
         hipLaunchKernelGGL(k_merge<NPOL>, grd, blk, 0, s, a.grid, (const float *)I.partial,
                            (const int32_t *)I.tile_work, (const int32_t *)I.work_ids, I.nx, I.ny,
                            L.tile, I.ntx, I.nty, I.W, accumulate);
         MWG_HIP(hipGetLastError());
+    }
+    if (I.timing) {
+        MWG_HIP(hipEventRecord(I.tev[2], s));
+        I.timed = true;
     }
     return Status::Ok();
 }
@@ -669,6 +554,20 @@ size_t wavetiles_lds(int npol, int T, int W, int O, int waves) {
 size_t scatter_lds(int npol, int T, int W, int O) {
     const int R = T + W - 1, STR = tile_stride(R, W), PL = tile_plane(R, STR);
     return 4 * ((size_t)2 * npol * PL + (size_t)O * W);
+}
+
+// The merge flush's per-work-item tile buffer, sized for the current schedule.
+Status ensure_partial(Instance &I, hipStream_t s) {
+    (void)s;
+    const int R = I.L.tile + I.W - 1;
+    const size_t need = sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * I.npol * R * R;
+    if (I.partial_bytes < need) {
+        void *p;
+        MWG_TRY(I.arena.alloc(&p, need));
+        I.partial = (float *)p;
+        I.partial_bytes = need;
+    }
+    return Status::Ok();
 }
 
 Status launch_fill_zero(void *ptr, size_t nbytes, hipStream_t s) {

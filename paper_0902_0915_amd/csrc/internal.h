@@ -59,6 +59,7 @@ struct Launch {
     int order = 1;     // 1 cell-sorted, 2 input order within tile
     int variant = 1;   // gridder variant
     int flush = 1;     // 1 atomic, 2 deterministic merge
+    int schedule = 1;  // 1 largest first, 2 Z-order chunks per XCD
 };
 
 struct WorkItem {
@@ -78,6 +79,15 @@ struct Instance {
     Launch L;
     int ntx = 0, nty = 0, ntiles_nonempty = 0, nwork = 0;
     int max_work_groups = 0;  // largest work item
+    int sorted_tile = 0, sorted_order = 0;   // the (tile, order) perm is currently sorted by
+    std::vector<int32_t> h_tstart, h_tend;  // tile bounds of that sort (host)
+    size_t cap_work = 0, cap_tiles = 0;      // capacities of work / tile_work / work_ids
+    // optional timing of the gridder and merge launches (mw_plan_set_timing)
+    bool timing = false;
+    hipEvent_t tev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
+    int xcd_start[9] = {0};   // schedule 2: first logical workgroup of each XCD's chunk
+    int xcd_wgs = 0;          // schedule 2: workgroups per XCD in the launch grid
     // device arrays (owned by arena)
     DevArena arena;
     uint32_t *pos = nullptr;      // [ngroups] packed, original order

@@ -430,36 +430,43 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     if (keybits > 31) return make_error(MW_ERR_UNSUPPORTED, "sort key wider than 31 bits");
     const uint32_t sentinel = (keybits >= 32) ? 0xFFFFFFFFu : ((1u << keybits) - 1u);
 
-    Tmp keys, keys2, vals, vals2;
-    MWG_TRY(keys.alloc(4 * ng));
-    MWG_TRY(keys2.alloc(4 * ng));
-    MWG_TRY(vals.alloc(4 * ng));
-    MWG_TRY(vals2.alloc(4 * ng));
-    uint32_t *skeys = nullptr, *sperm = nullptr;
-    if (ng > 0) {
-        hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, L.order,
-                           sentinel, keys.as<uint32_t>());
-        MWG_HIP(hipGetLastError());
-        MWG_TRY(radix_sort(keys.as<uint32_t>(), keys2.as<uint32_t>(), vals.as<uint32_t>(),
-                           vals2.as<uint32_t>(), ng, keybits, &skeys, &sperm, s));
-        MWG_HIP(hipMemcpyAsync(I.perm, sperm, 4 * ng, hipMemcpyDeviceToDevice, s));
-    }
     const int64_t nk = I.nkept;
-    // tile bounds
-    Tmp tstart, tend;
-    MWG_TRY(tstart.alloc(4 * ntiles));
-    MWG_TRY(tend.alloc(4 * ntiles));
-    MWG_TRY(launch_fill_u32(tstart.as<uint32_t>(), ntiles, 0, s));
-    MWG_TRY(launch_fill_u32(tend.as<uint32_t>(), ntiles, 0, s));
-    if (nk > 0) {
-        hipLaunchKernelGGL(k_tile_bounds, dim3(grid1d(nk)), dim3(kBlock), 0, s, skeys, nk,
-                           cellbits, tstart.as<int32_t>(), tend.as<int32_t>());
-        MWG_HIP(hipGetLastError());
+    const bool resort = !(L.tile == I.sorted_tile && L.order == I.sorted_order);
+    if (resort) {
+        Tmp keys, keys2, vals, vals2;
+        MWG_TRY(keys.alloc(4 * ng));
+        MWG_TRY(keys2.alloc(4 * ng));
+        MWG_TRY(vals.alloc(4 * ng));
+        MWG_TRY(vals2.alloc(4 * ng));
+        uint32_t *skeys = nullptr, *sperm = nullptr;
+        if (ng > 0) {
+            hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, L.order,
+                               sentinel, keys.as<uint32_t>());
+            MWG_HIP(hipGetLastError());
+            MWG_TRY(radix_sort(keys.as<uint32_t>(), keys2.as<uint32_t>(), vals.as<uint32_t>(),
+                               vals2.as<uint32_t>(), ng, keybits, &skeys, &sperm, s));
+            MWG_HIP(hipMemcpyAsync(I.perm, sperm, 4 * ng, hipMemcpyDeviceToDevice, s));
+        }
+        // tile bounds
+        Tmp tstart, tend;
+        MWG_TRY(tstart.alloc(4 * ntiles));
+        MWG_TRY(tend.alloc(4 * ntiles));
+        MWG_TRY(launch_fill_u32(tstart.as<uint32_t>(), ntiles, 0, s));
+        MWG_TRY(launch_fill_u32(tend.as<uint32_t>(), ntiles, 0, s));
+        if (nk > 0) {
+            hipLaunchKernelGGL(k_tile_bounds, dim3(grid1d(nk)), dim3(kBlock), 0, s, skeys, nk,
+                               cellbits, tstart.as<int32_t>(), tend.as<int32_t>());
+            MWG_HIP(hipGetLastError());
+        }
+        I.h_tstart.assign(ntiles, 0);
+        I.h_tend.assign(ntiles, 0);
+        MWG_HIP(hipMemcpyAsync(I.h_tstart.data(), tstart.p, 4 * ntiles, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipMemcpyAsync(I.h_tend.data(), tend.p, 4 * ntiles, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipStreamSynchronize(s));
+        I.sorted_tile = L.tile;
+        I.sorted_order = L.order;
     }
-    std::vector<int32_t> hs(ntiles), he(ntiles);
-    MWG_HIP(hipMemcpyAsync(hs.data(), tstart.p, 4 * ntiles, hipMemcpyDeviceToHost, s));
-    MWG_HIP(hipMemcpyAsync(he.data(), tend.p, 4 * ntiles, hipMemcpyDeviceToHost, s));
-    MWG_HIP(hipStreamSynchronize(s));
+    const std::vector<int32_t> &hs = I.h_tstart, &he = I.h_tend;
 
     std::vector<WorkItem> items;
     int nonempty = 0;
@@ -477,9 +484,46 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
             items.push_back(w);
         }
     }
-    std::stable_sort(items.begin(), items.end(), [](const WorkItem &a, const WorkItem &b) {
-        return (a.end - a.begin) > (b.end - b.begin);
-    });
+    if (L.schedule == 2) {
+        // Z-order of tile coordinates (the split pieces of a tile stay together), so that
+        // consecutive work items cover neighbouring tiles and share cached lines.
+        auto morton = [ntx](int32_t t) {
+            uint32_t x = (uint32_t)(t % ntx), y = (uint32_t)(t / ntx), m = 0;
+            for (int b = 0; b < 16; b++) m |= ((x >> b) & 1u) << (2 * b) | ((y >> b) & 1u) << (2 * b + 1);
+            return m;
+        };
+        std::stable_sort(items.begin(), items.end(), [&](const WorkItem &a, const WorkItem &b) {
+            return morton(a.tile) < morton(b.tile);
+        });
+    } else {
+        std::stable_sort(items.begin(), items.end(), [](const WorkItem &a, const WorkItem &b) {
+            return (a.end - a.begin) > (b.end - b.begin);
+        });
+    }
+    // Schedule 2: the launch's workgroups are dealt to the 8 XCDs round-robin by index; the
+    // logical workgroups (wg_waves consecutive work items each) are cut into 8 contiguous
+    // chunks of about equal total groups, chunk x served by the workgroups of XCD x.
+    {
+        const int nw = L.wg_waves;
+        const int nlog = (int)((items.size() + nw - 1) / nw);
+        std::vector<int64_t> wsum(nlog + 1, 0);
+        for (int b = 0; b < nlog; b++) {
+            int64_t s_ = 0;
+            for (int k = b * nw; k < std::min<int>((int)items.size(), (b + 1) * nw); k++)
+                s_ += items[k].end - items[k].begin;
+            wsum[b + 1] = wsum[b] + s_;
+        }
+        I.xcd_start[0] = 0;
+        int maxlen = 0;
+        for (int x = 1; x <= 8; x++) {
+            const int64_t target = wsum[nlog] * x / 8;
+            int b = I.xcd_start[x - 1];
+            while (b < nlog && wsum[b] < target) b++;
+            I.xcd_start[x] = (x == 8) ? nlog : b;
+            maxlen = std::max(maxlen, I.xcd_start[x] - I.xcd_start[x - 1]);
+        }
+        I.xcd_wgs = maxlen;
+    }
     // CSR of work items per tile (for the deterministic merge flush)
     std::vector<int32_t> tw(ntiles + 1, 0), ids(items.size());
     for (const WorkItem &w : items) tw[w.tile + 1]++;
@@ -497,12 +541,18 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     I.max_work_groups = 0;
     for (const WorkItem &w : items) I.max_work_groups = std::max(I.max_work_groups, w.end - w.begin);
     void *p;
-    MWG_TRY(I.arena.alloc(&p, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)));
-    I.work = (WorkItem *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * (ntiles + 1)));
-    I.tile_work = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(ids.size(), 1)));
-    I.work_ids = (int32_t *)p;
+    if (I.cap_work < std::max<size_t>(items.size(), 1)) {
+        I.cap_work = std::max<size_t>(items.size(), 1);
+        MWG_TRY(I.arena.alloc(&p, sizeof(WorkItem) * I.cap_work));
+        I.work = (WorkItem *)p;
+        MWG_TRY(I.arena.alloc(&p, 4 * I.cap_work));
+        I.work_ids = (int32_t *)p;
+    }
+    if (I.cap_tiles < (size_t)ntiles + 1) {
+        I.cap_tiles = (size_t)ntiles + 1;
+        MWG_TRY(I.arena.alloc(&p, 4 * I.cap_tiles));
+        I.tile_work = (int32_t *)p;
+    }
     if (!items.empty())
         MWG_HIP(hipMemcpyAsync(I.work, items.data(), sizeof(WorkItem) * items.size(),
                                hipMemcpyHostToDevice, s));
@@ -511,9 +561,11 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         MWG_HIP(hipMemcpyAsync(I.work_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
     // Sorted per-group arrays follow the new permutation.
     if (nk > 0) {
-        hipLaunchKernelGGL(k_gather, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.perm, nk, I.nchan, I.pos,
-                           I.w_orig, I.ant_orig, I.kidx_orig, I.spos, I.sw, I.sant, I.skid);
-        MWG_HIP(hipGetLastError());
+        if (resort) {
+            hipLaunchKernelGGL(k_gather, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.perm, nk, I.nchan, I.pos,
+                               I.w_orig, I.ant_orig, I.kidx_orig, I.spos, I.sw, I.sant, I.skid);
+            MWG_HIP(hipGetLastError());
+        }
         if (!I.stacks) {
             const int R = L.tile + I.W - 1;
             hipLaunchKernelGGL(k_codes, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.spos, nk, tb,
@@ -567,7 +619,10 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         if (t->order) L.order = t->order;
         if (t->variant) L.variant = t->variant;
         if (t->flush) L.flush = t->flush;
+        if (t->schedule) L.schedule = t->schedule;
     }
+    if (L.schedule == 2 && L.variant != 4)
+        return make_error(MW_ERR_UNSUPPORTED, "schedule 2 is implemented for variant 4 only");
     if (I.stacks) {
         L.variant = 5;
         const size_t lds = stack_lds(I.npol, L.tile, L.wg_waves);

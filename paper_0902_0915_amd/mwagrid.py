@@ -42,14 +42,14 @@ class MwInstance(ctypes.Structure):
 
 class MwTuning(ctypes.Structure):
     _fields_ = [("tile", _i32), ("split", _i32), ("wg_waves", _i32), ("order", _i32),
-                ("variant", _i32), ("flush", _i32), ("autotune", _i32)]
+                ("variant", _i32), ("flush", _i32), ("autotune", _i32), ("schedule", _i32)]
 
 
 class MwPlanStats(ctypes.Structure):
     _fields_ = [("ngroups", _i64), ("nkept", _i64), ("nflagged", _i64), ("noutside", _i64),
                 ("ntiles", _i32), ("nwork", _i32), ("tile", _i32), ("split", _i32),
                 ("wg_waves", _i32), ("order", _i32), ("variant", _i32), ("flush", _i32),
-                ("plan_bytes", _i64)]
+                ("schedule", _i32), ("plan_bytes", _i64)]
 
 
 _PP = ctypes.POINTER(ctypes.c_void_p)
@@ -62,12 +62,16 @@ _lib.mw_plan_info.argtypes = [_vp, _i32, ctypes.POINTER(MwPlanStats)]
 _lib.mw_plan_positions.argtypes = [_vp, _i32, _vp]
 _lib.mw_plan_tables.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.mw_plan_destroy.argtypes = [_vp]
+_lib.mw_plan_set_timing.argtypes = [_vp, _i32]
+_lib.mw_plan_kernel_ms.argtypes = [_vp, _i32, ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float)]
 _lib.mw_last_error.argtypes = []
 _lib.mw_last_error.restype = ctypes.c_char_p
 _lib.mw_abi_version.argtypes = []
 _lib.mw_abi_version.restype = _i32
 for _f in ("mw_grid_plan", "mw_grid", "mw_degrid", "mw_image", "mw_plan_info",
-           "mw_plan_positions", "mw_plan_tables", "mw_plan_destroy"):
+           "mw_plan_positions", "mw_plan_tables", "mw_plan_destroy", "mw_plan_set_timing",
+           "mw_plan_kernel_ms"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -260,6 +264,15 @@ class Plan:
         _check(_lib.mw_plan_tables(self.handle, inst, tab.ctypes.data, cx.ctypes.data,
                                    cy.ctypes.data))
         return tab, cx, cy
+
+    def set_timing(self, enable=True):
+        _check(_lib.mw_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def kernel_ms(self, inst=0):
+        """(gridder ms, merge ms) of the last timed grid call of instance ``inst``."""
+        g, m = ctypes.c_float(), ctypes.c_float()
+        _check(_lib.mw_plan_kernel_ms(self.handle, inst, ctypes.byref(g), ctypes.byref(m)))
+        return g.value, m.value
 
     # ---- compute -----------------------------------------------------------------------
     def _as_list(self, x):

@@ -306,3 +306,36 @@ def test_state_errors_on_gpu(mw, tiny):
         _plan(mw, synth.mwa_scale(seed=1, nant=8, nchan=1, ntime=1, npol=4, n=64, nsrc=1),
               tuning=dict(tile=64, wg_waves=16))
     assert e.value.status == mw.MW_ERR_UNSUPPORTED
+
+
+def test_autotune_and_cache(mw, small_mwa, tmp_path, monkeypatch):
+    wl = small_mwa
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("MW_TUNE_CACHE", str(cache))
+    ref = oracle_grid(wl, wl.vis)
+    with _plan(mw, wl, tuning=dict(autotune=1), with_ants=False) as plan:
+        got = to_host(plan.grid(to_dev(wl.vis)))
+        chosen = plan.info(0)
+    assert nl2(got, ref) <= TOL
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and '"key": "gfx950' in lines[0]
+    # a second plan takes the cached launch without searching again
+    with _plan(mw, wl, tuning=dict(autotune=1), with_ants=False) as plan2:
+        again = plan2.info(0)
+        got2 = to_host(plan2.grid(to_dev(wl.vis)))
+    assert len(cache.read_text().strip().splitlines()) == 1
+    for k in ("tile", "split", "wg_waves", "variant", "flush", "schedule"):
+        assert again[k] == chosen[k]
+    assert nl2(got2, ref) <= TOL
+
+
+def test_kernel_timing(mw, small_mwa):
+    wl = small_mwa
+    with _plan(mw, wl, with_ants=False) as plan:
+        with pytest.raises(mw.MwError):
+            plan.kernel_ms(0)
+        plan.set_timing(True)
+        plan.grid(to_dev(wl.vis))
+        g, m = plan.kernel_ms(0)
+        assert g > 0.0 and m > 0.0
+        plan.set_timing(False)
