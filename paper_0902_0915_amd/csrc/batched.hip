@@ -1,9 +1,9 @@
 // Batched form of a multi-instance plan: many uneven gridding instances (snapshots,
-// channels) in one persistent launch, replayed from a captured hipGraph.
+// channels) in one launch sequence, replayed from a captured hipGraph.
 //
-// Gridding: a persistent kernel whose wavefronts pull (instance, work item) pairs from a
-// device counter, largest first over all instances, and grid each one with the wave-tile
-// body shared with the single-instance gridder (gridder_core.h); then one merge launch over
+// Gridding: one launch over the (instance, work item) pairs of all instances, one pair per
+// wavefront, in instance order; each item is gridded with the wave-tile body shared with
+// the single-instance gridder (gridder_core.h). Then one merge launch over
 // the cells of every instance's grid. Degridding: one launch over all instances' work items
 // with the shared degrid body (degrid_core.h), after one prologue launch that zeroes the
 // outputs of dropped groups and the gain gradients.
@@ -48,7 +48,7 @@ struct BatchItem {
 
 struct Batch {
     int ninst = 0, npol = 1, W = 7, O = 8, T = 8, waves = 8, STR = 0, PL = 0, nitems = 0;
-    int grid_blocks = 0;     // persistent gridder workgroups
+    int grid_blocks = 0;     // gridder workgroups (waves of them, one work item per wave)
     int64_t merge_blocks = 0, prologue_n = 0;
     int ant_in_lds = 0;
     size_t grid_lds = 0, degrid_lds = 0;
@@ -57,7 +57,6 @@ struct Batch {
     hipEvent_t desc_ev = nullptr;
     bool desc_pending = false;
     BatchItem *d_items = nullptr;
-    uint32_t *d_counter = nullptr;
     int64_t *d_merge_start = nullptr, *d_pro_start = nullptr;
     const float *tab8 = nullptr;
     float tapk[16 * 8] = {0};
@@ -69,14 +68,22 @@ struct Batch {
 struct BatchGridArgs {
     const BatchDesc *desc;
     const BatchItem *items;
-    uint32_t *counter;
     const float *tab8;
     int nitems, O, T, STR, PL;
     float tapk[16 * 8];
 };
 
-__global__ void k_reset_counter(uint32_t *c) {
-    if (threadIdx.x == 0) *c = 0u;
+// Wave-uniform copies of values loaded from the descriptor table. Without them the
+// compiler may keep such values in VGPRs, and every loop of the item body then becomes an
+// exec-masked divergent loop.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <class T>
+__device__ inline T *uni(T *p) {
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
 }
 
 template <int NPOL, int W>
@@ -89,45 +96,40 @@ __global__ __launch_bounds__(1024) void k_grid_batched(BatchGridArgs a) {
     float *ltab = smem;
     for (int i = tid; i < ntab; i += blockDim.x) ltab[i] = a.tab8[i];
     __syncthreads();
+    const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    if (w >= a.nitems) return;
     const int R = a.T + W - 1;
     float *tile = smem + ntab + wave * (NC * a.PL + 64 * NC);
-    for (;;) {
-        uint32_t w = 0;
-        if (lane == 0) w = atomicAdd(a.counter, 1u);
-        w = (uint32_t)__builtin_amdgcn_readfirstlane((int)w);
-        if ((int)w >= a.nitems) break;
-        const BatchItem it = a.items[w];
-        const BatchDesc &d = a.desc[it.inst];
-        const WorkItem wk = d.work[it.item];
-        for (int i = lane; i < NC * a.PL; i += 64) tile[i] = 0.0f;
-        ItemCtx c;
-        c.tile = tile;
-        c.sv = tile + NC * a.PL;
-        c.vis = d.vis;
-        c.gains = d.gains;
-        c.perm = d.perm;
-        c.scode = d.scode;
-        c.sant = d.sant;
-        c.sw = d.sw;
-        c.tapk = a.tapk;
-        c.ltab = ltab;
-        c.grid = d.grid;
-        c.partial = d.partial + (int64_t)it.item * NC * R * R;
-        c.wb = wk.begin;
-        c.we = wk.end;
-        c.tx0 = (wk.tile % d.ntx) * a.T;
-        c.ty0 = (wk.tile / d.ntx) * a.T;
-        c.T = a.T;
-        c.STR = a.STR;
-        c.PL = a.PL;
-        c.nx = d.nx;
-        c.ny = d.ny;
-        c.flush = 2;
-        wavetile_item<NPOL, W>(c, lane);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    const BatchItem it = a.items[w];
+    const int inst = uni(it.inst), item = uni(it.item);
+    const BatchDesc &d = a.desc[inst];
+    const WorkItem wk = d.work[item];
+    const int ntx = uni(d.ntx), wtile = uni(wk.tile);
+    for (int i = lane; i < NC * a.PL; i += 64) tile[i] = 0.0f;
+    ItemCtx c;
+    c.tile = tile;
+    c.sv = tile + NC * a.PL;
+    c.vis = uni(d.vis);
+    c.gains = uni(d.gains);
+    c.perm = uni(d.perm);
+    c.scode = uni(d.scode);
+    c.sant = uni(d.sant);
+    c.sw = uni(d.sw);
+    c.tapk = a.tapk;
+    c.ltab = ltab;
+    c.grid = uni(d.grid);
+    c.partial = uni(d.partial) + (int64_t)item * NC * R * R;
+    c.wb = uni(wk.begin);
+    c.we = uni(wk.end);
+    c.tx0 = (wtile % ntx) * a.T;
+    c.ty0 = (wtile / ntx) * a.T;
+    c.T = a.T;
+    c.STR = a.STR;
+    c.PL = a.PL;
+    c.nx = uni(d.nx);
+    c.ny = uni(d.ny);
+    c.flush = 2;
+    wavetile_item<NPOL, W>(c, lane);
 }
 
 __device__ inline int find_inst(const int64_t *start, int n, int64_t b) {
@@ -140,17 +142,17 @@ __device__ inline int find_inst(const int64_t *start, int n, int64_t b) {
 }
 
 template <int NPOL>
-__global__ void k_merge_batched(const BatchDesc *desc, const int64_t *start, int ninst, int T, int W) {
+__global__ __launch_bounds__(kMergeB * kMergeB) void k_merge_batched(const BatchDesc *desc, const int64_t *start,
+                                                                     int ninst, int lgT, int W) {
+    __shared__ int2 rng[kMergeTiles];
     const int64_t b = blockIdx.x;
     const int inst = find_inst(start, ninst, b);
     const BatchDesc &d = desc[inst];
-    const int64_t local = b - start[inst];
-    const int bpr = (d.nx + 255) / 256;
-    const int y = (int)(local / bpr);
-    const int x = (int)(local % bpr) * 256 + threadIdx.x;
-    if (x >= d.nx || y >= d.ny) return;
-    merge_cell<NPOL>(d.grid, d.partial, d.tile_work, d.work_ids, d.nx, d.ny, T, d.ntx, d.nty, W,
-                     d.accumulate, x, y);
+    const int local = (int)(b - start[inst]);
+    const int bpr = (d.nx + kMergeB - 1) / kMergeB;
+    const int by = local / bpr, bx = local - by * bpr;
+    merge_block<NPOL>(d.grid, d.partial, d.tile_work, d.work_ids, d.nx, d.ny, lgT, d.ntx, d.nty, W,
+                      d.accumulate, bx * kMergeB, by * kMergeB, rng);
 }
 
 // Zeroes the adjoint outputs of dropped groups (entries [0, start[ninst]) of the dropped
@@ -210,11 +212,9 @@ int plane2(int R, int STR, int W) {
 
 template <int NPOL>
 Status enqueue_grid(Batch &B, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, B.d_counter);
     BatchGridArgs a;
     a.desc = B.d_desc;
     a.items = B.d_items;
-    a.counter = B.d_counter;
     a.tab8 = B.tab8;
     a.nitems = B.nitems;
     a.O = B.O;
@@ -230,8 +230,8 @@ Status enqueue_grid(Batch &B, hipStream_t s) {
     default: return make_error(MW_ERR_UNSUPPORTED, "batched gridder needs W in {3, 5, 7}");
     }
     MWG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_merge_batched<NPOL>, dim3((unsigned)B.merge_blocks), dim3(256), 0, s, B.d_desc,
-                       (const int64_t *)B.d_merge_start, B.ninst, B.T, B.W);
+    hipLaunchKernelGGL(k_merge_batched<NPOL>, dim3((unsigned)B.merge_blocks), dim3(kMergeB * kMergeB), 0, s,
+                       B.d_desc, (const int64_t *)B.d_merge_start, B.ninst, ilog2(B.T), B.W);
     MWG_HIP(hipGetLastError());
     return Status::Ok();
 }
@@ -368,27 +368,16 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         d.ndropped = (int)(I.ngroups - I.nkept);
         max_nant = std::max(max_nant, I.nant);
         for (int w = 0; w < I.nwork; w++) items.push_back({i, w});
-        mstart[i + 1] = mstart[i] + (int64_t)I.ny * ((I.nx + 255) / 256);
+        mstart[i + 1] = mstart[i] + (int64_t)((I.ny + kMergeB - 1) / kMergeB) * ((I.nx + kMergeB - 1) / kMergeB);
         pstart[i + 1] = pstart[i] + d.ndropped;
     }
     // second half: gain-gradient entries, numbered after all dropped entries
     for (int i = 0; i < B->ninst; i++) pstart[B->ninst + i + 1] = pstart[B->ninst + i] + desc[i].nant;
     B->prologue_n = pstart[2 * B->ninst];
-    // largest work items first over all instances
-    {
-        // sizes need host copies of the work lists
-        std::vector<std::vector<WorkItem>> hw(B->ninst);
-        for (int i = 0; i < B->ninst; i++) {
-            hw[i].resize(P.inst[i]->nwork);
-            if (P.inst[i]->nwork)
-                MWG_HIP(hipMemcpy(hw[i].data(), P.inst[i]->work, sizeof(WorkItem) * P.inst[i]->nwork,
-                                  hipMemcpyDeviceToHost));
-        }
-        std::stable_sort(items.begin(), items.end(), [&](const BatchItem &x, const BatchItem &y) {
-            const WorkItem &a = hw[x.inst][x.item], &b = hw[y.inst][y.item];
-            return (a.end - a.begin) > (b.end - b.begin);
-        });
-    }
+    // Items stay in instance order (largest first within an instance, as each work list is
+    // built): the waves in flight then gather from one or two instances' visibilities at a
+    // time, which stay in cache. Interleaving all instances largest-first spreads the random
+    // gathers over every instance at once and runs ~4x slower.
     B->nitems = (int)items.size();
     B->merge_blocks = mstart[B->ninst];
     void *p;
@@ -404,8 +393,6 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     B->d_items = (BatchItem *)p;
     if (!items.empty())
         MWG_HIP(hipMemcpy(B->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
-    MWG_TRY(B->arena.alloc(&p, 64));
-    B->d_counter = (uint32_t *)p;
     MWG_TRY(B->arena.alloc(&p, sizeof(int64_t) * mstart.size()));
     B->d_merge_start = (int64_t *)p;
     MWG_HIP(hipMemcpy(B->d_merge_start, mstart.data(), sizeof(int64_t) * mstart.size(), hipMemcpyHostToDevice));
@@ -416,11 +403,7 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     MWG_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     // launch shapes
     B->grid_lds = wavetiles_lds(B->npol, B->T, B->W, B->O, B->waves);
-    int dev = 0, ncu = 0;
-    MWG_HIP(hipGetDevice(&dev));
-    MWG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = std::max<int>(1, (int)((160 * 1024) / std::max<size_t>(B->grid_lds, 1)));
-    B->grid_blocks = std::max(1, std::min(ncu * per_cu, (B->nitems + B->waves - 1) / B->waves));
+    B->grid_blocks = std::max(1, (B->nitems + B->waves - 1) / B->waves);
     const int Rd = B->T + B->W - 1;
     B->degrid_lds = sizeof(float2) * (size_t)B->npol * Rd * Rd + 4 * (size_t)((B->O * B->W + 1) & ~1);
     B->ant_in_lds = (max_nant > 0 && B->degrid_lds + sizeof(float2) * (size_t)max_nant <= 64 * 1024) ? 1 : 0;

@@ -463,13 +463,13 @@ __global__ __launch_bounds__(1024) void k_grid_scatter(GridArgs a, int flush) {
 // Merge pass of flush 2: every grid cell sums the partial tiles of all work items whose
 // (haloed) tile covers it, in a fixed order.
 template <int NPOL>
-__global__ void k_merge(float2 *grid, const float *partial, const int32_t *tile_work,
-                        const int32_t *work_ids, int nx, int ny, int T, int ntx, int nty, int W,
-                        int accumulate) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= nx) return;
-    merge_cell<NPOL>(grid, partial, tile_work, work_ids, nx, ny, T, ntx, nty, W, accumulate, x, y);
+__global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const float *partial,
+                                                              const int32_t *tile_work, const int32_t *work_ids,
+                                                              int nx, int ny, int lgT, int ntx, int nty, int W,
+                                                              int accumulate) {
+    __shared__ int2 rng[kMergeTiles];
+    merge_block<NPOL>(grid, partial, tile_work, work_ids, nx, ny, lgT, ntx, nty, W, accumulate,
+                      blockIdx.x * kMergeB, blockIdx.y * kMergeB, rng);
 }
 
 template <int NPOL>
@@ -521,10 +521,10 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
     }
     if (I.timing) MWG_HIP(hipEventRecord(I.tev[1], s));
     if (flush == 2) {
-        dim3 blk(256), grd((I.nx + 255) / 256, I.ny);
+        dim3 blk(kMergeB * kMergeB), grd((I.nx + kMergeB - 1) / kMergeB, (I.ny + kMergeB - 1) / kMergeB);
         hipLaunchKernelGGL(k_merge<NPOL>, grd, blk, 0, s, a.grid, (const float *)I.partial,
                            (const int32_t *)I.tile_work, (const int32_t *)I.work_ids, I.nx, I.ny,
-                           L.tile, I.ntx, I.nty, I.W, accumulate);
+                           ilog2(L.tile), I.ntx, I.nty, I.W, accumulate);
         MWG_HIP(hipGetLastError());
     }
     if (I.timing) {

@@ -45,6 +45,13 @@ struct DevArena {
     void release();
 };
 
+// Smallest r with 2^r >= v (the exponent of a power-of-two tile size).
+inline int ilog2(int v) {
+    int r = 0;
+    while ((1 << r) < v) r++;
+    return r;
+}
+
 // Packed per-group position: cx | cy << 12 | (px + O/2) << 24 | (py + O/2) << 28.
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 __host__ __device__ inline uint32_t pack_pos(int cx, int cy, int pxo, int pyo) {

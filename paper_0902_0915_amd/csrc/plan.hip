@@ -358,11 +358,6 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-int ilog2(int v) {
-    int r = 0;
-    while ((1 << r) < v) r++;
-    return r;
-}
 
 int bitlength(uint64_t v) {
     int r = 0;
@@ -584,7 +579,10 @@ size_t scatter_lds(int npol, int T, int W, int O);
 
 static Launch default_launch(const Instance &I) {
     Launch L;
-    L.split = 8192;
+    // Work-item size: about 4096 items per instance (enough to fill the chip's wave slots
+    // with a short tail), between 256 and 8192 groups.
+    L.split = 256;
+    while (L.split < 8192 && (int64_t)L.split * 4096 < I.nkept) L.split *= 2;
     L.order = 1;
     if (I.stacks) {
         // gather by output tile, one private tile per wavefront
