@@ -95,7 +95,8 @@ typedef struct {
     int32_t tile;       /* uv tile edge in cells: 8, 16, 32 or 64 (8 needs W <= 15) */
     int32_t split;      /* max groups per work item (heavy tiles are split), >= 64 */
     int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 */
-    int32_t order;      /* 1 = groups sorted by cell within a tile, 2 = input order */
+    int32_t order;      /* 1 = groups sorted by cell (then row sub-position) within a tile,
+                           2 = input order */
     int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes, 3 = scatter,
                            4 = column lanes with a private tile per wavefront,
                            5 = kernel stacks, gathered by output tile (chosen for stacks) */

@@ -99,16 +99,17 @@ __global__ __launch_bounds__(1024) void k_grid_batched(BatchGridArgs a) {
     const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
     if (w >= a.nitems) return;
     const int R = a.T + W - 1;
-    float *tile = smem + ntab + wave * (NC * a.PL + 64 * NC);
+    float *stage = smem + ntab + wave * wavetile_per_wave(NC, a.PL);
     const BatchItem it = a.items[w];
     const int inst = uni(it.inst), item = uni(it.item);
     const BatchDesc &d = a.desc[inst];
     const WorkItem wk = d.work[item];
     const int ntx = uni(d.ntx), wtile = uni(wk.tile);
+    float *tile = stage + kStageFloats;
     for (int i = lane; i < NC * a.PL; i += 64) tile[i] = 0.0f;
     ItemCtx c;
     c.tile = tile;
-    c.sv = tile + NC * a.PL;
+    c.sv = stage;
     c.vis = uni(d.vis);
     c.gains = uni(d.gains);
     c.perm = uni(d.perm);

@@ -394,10 +394,10 @@ __global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, 
     const int widx = lb * nwaves + wave;
     if (widx >= nwork) return;
     const int R = a.T + W - 1;
-    const int per_wave = NC * a.plane + 64 * NC;
+    const int per_wave = wavetile_per_wave(NC, a.plane);
     ItemCtx c;
-    c.tile = smem + ntab + wave * per_wave;
-    c.sv = c.tile + NC * a.plane;
+    c.sv = smem + ntab + wave * per_wave;
+    c.tile = c.sv + kStageFloats;
     for (int i = lane; i < NC * a.plane; i += 64) c.tile[i] = 0.0f;
     const WorkItem wk = a.work[widx];
     c.vis = a.vis;
@@ -548,7 +548,7 @@ size_t collanes_lds(int npol, int T, int W, int O, int waves) {
 
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves) {
     const int R = T + W - 1, PL = tile_plane2(R, R, W);
-    return 4 * ((size_t)O * 8 + (size_t)waves * (2 * npol * PL + 64 * 2 * npol));
+    return 4 * ((size_t)O * 8 + (size_t)waves * wavetile_per_wave(2 * npol, PL));
 }
 
 size_t scatter_lds(int npol, int T, int W, int O) {

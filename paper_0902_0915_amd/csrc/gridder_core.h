@@ -63,8 +63,27 @@ __device__ inline void wave_tile_add(float *p, int STR, int sg, const float (&ac
         if (sg + NSG * k < W) p[NSG * k * STR] = old[k] + acc[k];
 }
 
+// Per-wave staging area of the wave-tile gridder: 32 groups at a time, each as its 2 * npol
+// visibility components (slots 0..7) and its column-tap row T[px][0..7] (slots 8..15).
+constexpr int kStageGroups = 32;
+constexpr int kStageStride = 16;
+constexpr int kStageFloats = kStageGroups * kStageStride;
+
+// LDS floats per wave of the wave-tile gridder: the staging area, then the tile (NC planes
+// of PL floats), rounded so that every wave's staging area stays 16-byte aligned.
+__host__ __device__ inline int wavetile_per_wave(int nc, int pl) { return kStageFloats + ((nc * pl + 3) & ~3); }
+
 // Grids work item c with this wavefront (lanes as in variant 2) into its private tile and
 // writes the tile out. The tile must be zero on entry.
+//
+// The groups of an item arrive sorted by centre cell and, within a cell, by the row
+// sub-position py. The separable tap factorises the work: for a run of groups with the same
+// (cell, py), lane (component, column t) first sums T[px][t] * V over the run (one FMA per
+// group), and only at the end of the run multiplies that sum into its row accumulators with
+// the run's row taps T[py][s]. The row accumulators go to the LDS tile when the cell
+// changes. A group costs one FMA instead of W + 1; a run of equal (cell, py) costs W more.
+// Both operands of the per-group FMA come from the staging area at fixed offsets, eight
+// groups per LDS round trip, so the loop has no per-group address arithmetic.
 template <int NPOL, int W>
 __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
     constexpr int NC = 2 * NPOL;
@@ -80,17 +99,50 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
     const int sg = lane / (W * NC);
     const bool active = lane < W * NC * NSG;
     const int loff = active ? cc * PL + sg * STR + t : 0;
-    const float *vl = sv + cc;
-    const float *txl = ltab + t;
-    float acc[NR];
+    const float *vbase = sv + cc;     // staged group jl's component: vbase[jl * kStageStride]
+    const float *tbase = sv + 8 + t;  // and its column tap T[px][t]
+    float acc[NR], ty[NR];
 #pragma unroll
-    for (int k = 0; k < NR; k++) acc[k] = 0.0f;
-    int cur = -1;
+    for (int k = 0; k < NR; k++) {
+        acc[k] = 0.0f;
+        ty[k] = 0.0f;
+    }
+    float asum = 0.0f;
+    int cur = -1;     // current cell (offset in the tile), -1 before the first group
+    int curkey = -1;  // current (cell, py) key
 
-    // Software pipeline over batches of 64 groups. Lane j holds group j's code in a VGPR
-    // (read into a scalar register per group with v_readlane) and stages its visibilities
-    // in LDS; the next batch's codes and visibilities and the permutation two batches ahead
-    // are in flight while a batch is accumulated.
+    // Ends the current (cell, py) run and starts the one of code qj (a new cell if newcell).
+    auto start_run = [&](uint32_t qj, bool newcell) {
+#pragma unroll
+        for (int k = 0; k < NR; k++) acc[k] = fmaf(ty[k], asum, acc[k]);
+        asum = 0.0f;
+        if (newcell) {
+            if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
+#pragma unroll
+            for (int k = 0; k < NR; k++) acc[k] = 0.0f;
+            cur = (int)(qj & 0xFFFFu);
+        }
+        curkey = (int)(qj & 0xFF00FFFFu);
+        const int ty8 = (int)(qj >> 24);
+        if constexpr (NSG == 1) {
+            // every lane needs the whole row: two 16-byte reads of one address
+            const float4 *r = (const float4 *)(ltab + ty8);
+            const float4 r0 = r[0], r1 = r[1];
+            const float row[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int k = 0; k < NR; k++) ty[k] = row[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NR; k++) {
+                const int sr = sg + NSG * k;
+                ty[k] = ltab[ty8 + (sr < W ? sr : 0)];
+            }
+        }
+    };
+
+    // Software pipeline over batches of 64 groups: lane j holds group j's code and
+    // visibilities; the next batch's codes and visibilities and the permutation two batches
+    // ahead are in flight while a batch is accumulated.
     uint32_t gA = (wb + lane < we) ? c.perm[wb + lane] : 0u;
     uint32_t gB = (wb + 64 + lane < we) ? c.perm[wb + 64 + lane] : 0u;
     uint32_t qn = (wb + lane < we) ? c.scode[wb + lane] : 0u;
@@ -99,86 +151,73 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
 
     for (int base = wb; base < we; base += 64) {
         const int cnt = (we - base) < 64 ? (we - base) : 64;
-        if (lane < cnt) {
-            float *dst = sv + lane * NC;
-#pragma unroll
-            for (int p = 0; p < NPOL; p++) {
-                dst[2 * p] = vn[p].x;
-                dst[2 * p + 1] = vn[p].y;
-            }
-        }
         const uint32_t qcur = qn;
+        float2 vc[NPOL];
+#pragma unroll
+        for (int p = 0; p < NPOL; p++) vc[p] = vn[p];
         if (base + 64 + lane < we) {
             core_fetch<NPOL>(c, base + 64 + lane, gB, vn);
             qn = c.scode[base + 64 + lane];
         }
         gB = (base + 128 + lane < we) ? c.perm[base + 128 + lane] : 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // Runs of equal centre cell: lane j flags whether group j starts a new run.
+        // Run boundaries: lane j flags whether group j starts a new (cell, py) run and
+        // whether it starts a new cell.
         const int cellj = (int)(qcur & 0xFFFFu);
-        int prevj = __shfl_up(cellj, 1, 64);
-        if (lane == 0) prevj = cur;
-        const uint64_t starts = __ballot(lane < cnt && cellj != prevj);
-        int j = 0;
-        while (j < cnt) {
-            const uint64_t later = (j + 1 < 64) ? (starts >> (j + 1)) : 0ull;
-            const int e = later ? (j + 1 + (int)__builtin_ctzll(later)) : cnt;
-            if ((starts >> j) & 1ull) {
-                if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
-#pragma unroll
-                for (int k = 0; k < NR; k++) acc[k] = 0.0f;
-                cur = (int)((uint32_t)__builtin_amdgcn_readlane((int)qcur, j) & 0xFFFFu);
-            }
-            // branch-free accumulation over the run [j, e), four groups per step so that
-            // their LDS and scalar loads share one wait
-            int jj = j;
-            for (; jj + 4 <= e; jj += 4) {
-                uint32_t q[4];
-                float va[4];
-#pragma unroll
-                for (int u = 0; u < 4; u++) q[u] = (uint32_t)__builtin_amdgcn_readlane((int)qcur, jj + u);
-#pragma unroll
-                for (int u = 0; u < 4; u++) va[u] = vl[(jj + u) * NC] * txl[(q[u] >> 16) & 0xFFu];
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int tyo = (int)(q[u] >> 24);
-                    if constexpr (NSG == 1) {
-                        const float *tyr = c.tapk + tyo;
-#pragma unroll
-                        for (int k = 0; k < NR; k++) acc[k] = fmaf(tyr[k], va[u], acc[k]);
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < NR; k++) {
-                            const int sr = sg + NSG * k;
-                            acc[k] = fmaf(ltab[tyo + (sr < W ? sr : 0)], va[u], acc[k]);
-                        }
-                    }
-                }
-            }
-            for (; jj < e; jj++) {
-                const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)qcur, jj);
-                const int tyo = (int)(q >> 24);
-                const float va = vl[jj * NC] * txl[(q >> 16) & 0xFFu];
-                if constexpr (NSG == 1) {
-                    const float *tyr = c.tapk + tyo;
-#pragma unroll
-                    for (int k = 0; k < NR; k++) acc[k] = fmaf(tyr[k], va, acc[k]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < NR; k++) {
-                        const int sr = sg + NSG * k;
-                        acc[k] = fmaf(ltab[tyo + (sr < W ? sr : 0)], va, acc[k]);
-                    }
-                }
-            }
-            j = e;
+        const int keyj = (int)(qcur & 0xFF00FFFFu);
+        int prevc = __shfl_up(cellj, 1, 64);
+        int prevk = __shfl_up(keyj, 1, 64);
+        if (lane == 0) {
+            prevc = cur;
+            prevk = curkey;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint64_t kstarts = __ballot(lane < cnt && keyj != prevk);
+        const uint64_t cstarts = __ballot(lane < cnt && cellj != prevc);
+        for (int h0 = 0; h0 < cnt; h0 += kStageGroups) {
+            // stage groups [h0, h0 + 32): visibilities and column-tap rows; positions past
+            // the item's end get zeros, so that whole blocks of 8 can be accumulated
+            const int jo = lane - h0;
+            if (jo >= 0 && jo < kStageGroups) {
+                float *dst = sv + jo * kStageStride;
+                const bool live = lane < cnt;
+                if constexpr (NPOL == 4) {
+                    ((float4 *)dst)[0] = live ? make_float4(vc[0].x, vc[0].y, vc[1].x, vc[1].y) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    ((float4 *)dst)[1] = live ? make_float4(vc[2].x, vc[2].y, vc[3].x, vc[3].y) : make_float4(0.f, 0.f, 0.f, 0.f);
+                } else if constexpr (NPOL == 2) {
+                    ((float4 *)dst)[0] = live ? make_float4(vc[0].x, vc[0].y, vc[1].x, vc[1].y) : make_float4(0.f, 0.f, 0.f, 0.f);
+                } else {
+                    ((float2 *)dst)[0] = live ? vc[0] : make_float2(0.f, 0.f);
+                }
+                const float4 *row = (const float4 *)(ltab + (live ? ((qcur >> 16) & 0xFFu) : 0u));
+                ((float4 *)(dst + 8))[0] = live ? row[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+                ((float4 *)(dst + 8))[1] = live ? row[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int hcnt = (cnt - h0) < kStageGroups ? (cnt - h0) : kStageGroups;
+            for (int jb = 0; jb < hcnt; jb += 8) {
+                float v8[8], t8[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    v8[u] = vbase[(jb + u) * kStageStride];
+                    t8[u] = tbase[(jb + u) * kStageStride];
+                }
+                const int j0 = h0 + jb;
+                const uint32_t ks = (uint32_t)(kstarts >> j0) & 0xFFu;  // run starts in this block
+                const uint32_t cs = (uint32_t)(cstarts >> j0) & 0xFFu;  // cell starts
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    if ((ks >> u) & 1u)
+                        start_run((uint32_t)__builtin_amdgcn_readlane((int)qcur, j0 + u), (cs >> u) & 1u);
+                    asum = fmaf(t8[u], v8[u], asum);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
+    start_run(0u, false);  // close the last run (the new run is never used)
     if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

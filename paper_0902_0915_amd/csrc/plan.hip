@@ -145,7 +145,9 @@ __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int orde
         const uint32_t cx = p & 0xFFFu, cy = (p >> 12) & 0xFFFu;
         const uint32_t tile = (cy >> tb) * (uint32_t)ntx + (cx >> tb);
         const uint32_t mask = (1u << tb) - 1u;
-        k = order == 1 ? (tile << (2 * tb)) | ((cy & mask) << tb) | (cx & mask) : tile;
+        // order 1: (tile, cell row, cell column, row sub-position)
+        k = order == 1 ? (tile << (2 * tb + 4)) | ((cy & mask) << (tb + 4)) | ((cx & mask) << 4) | (p >> 28)
+                       : tile;
     }
     keys[g] = k;
 }
@@ -410,7 +412,8 @@ int tile_stride_host(int R, int W) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Work list: sort by (tile[, cell]), tile bounds, split heavy tiles, largest first.
+// Work list: sort by (tile[, cell, row sub-position]), tile bounds, split heavy tiles,
+// largest first.
 // Rebuilt when the tuner changes the tile size, order or split.
 // ------------------------------------------------------------------------------------------
 Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
@@ -419,7 +422,7 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     if ((1 << tb) != L.tile) return make_error(MW_ERR_INVALID_ARG, "tile %d is not a power of two", L.tile);
     const int ntx = (I.nx + L.tile - 1) / L.tile, nty = (I.ny + L.tile - 1) / L.tile;
     const int64_t ntiles = (int64_t)ntx * nty;
-    const int cellbits = L.order == 1 ? 2 * tb : 0;
+    const int cellbits = L.order == 1 ? 2 * tb + 4 : 0; // key bits below the tile index
     const uint64_t maxkey = (uint64_t)ntiles << cellbits; // exclusive bound of valid keys
     const int keybits = bitlength(maxkey);
     if (keybits > 31) return make_error(MW_ERR_UNSUPPORTED, "sort key wider than 31 bits");
@@ -634,10 +637,16 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
             return make_error(MW_ERR_UNSUPPORTED, "variants 2 and 4 need 3 <= W <= 7 (W = %d)", I.W);
         if (L.variant == 1 && I.W * I.W > 64)
             return make_error(MW_ERR_UNSUPPORTED, "variant 1 needs W*W <= 64 (W = %d)", I.W);
-        const size_t lds = L.variant == 1   ? taplanes_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
-                           : L.variant == 2 ? collanes_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
-                           : L.variant == 4 ? wavetiles_lds(I.npol, L.tile, I.W, I.O, L.wg_waves)
-                                            : scatter_lds(I.npol, L.tile, I.W, I.O);
+        auto lds_of = [&](const Launch &X) {
+            return X.variant == 1   ? taplanes_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
+                   : X.variant == 2 ? collanes_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
+                   : X.variant == 4 ? wavetiles_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
+                                    : scatter_lds(I.npol, X.tile, I.W, I.O);
+        };
+        // private wave tiles of a large tile size may not fit: without an explicit variant,
+        // fall back to the shared-tile kernel of the same lane layout
+        if (L.variant == 4 && !(t && t->variant) && L.schedule != 2 && lds_of(L) > 160 * 1024) L.variant = 2;
+        const size_t lds = lds_of(L);
         if (lds > 160 * 1024)
             return make_error(MW_ERR_UNSUPPORTED, "launch needs %zu B of LDS (tile %d, npol %d)", lds,
                               L.tile, I.npol);
