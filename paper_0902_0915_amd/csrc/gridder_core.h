@@ -125,12 +125,10 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
         curkey = (int)(qj & 0xFF00FFFFu);
         const int ty8 = (int)(qj >> 24);
         if constexpr (NSG == 1) {
-            // every lane needs the whole row: two 16-byte reads of one address
-            const float4 *r = (const float4 *)(ltab + ty8);
-            const float4 r0 = r[0], r1 = r[1];
-            const float row[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+            // every lane needs the whole row: scalar loads from the kernel-argument copy of
+            // the table (an LDS broadcast would cost the LDS a full wave of reads)
 #pragma unroll
-            for (int k = 0; k < NR; k++) ty[k] = row[k];
+            for (int k = 0; k < NR; k++) ty[k] = c.tapk[ty8 + k];
         } else {
 #pragma unroll
             for (int k = 0; k < NR; k++) {
