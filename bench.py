@@ -35,6 +35,32 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 KERNEL_NAMES = {1: "k_grid_taplanes", 2: "k_grid_collanes", 3: "k_grid_scatter",
                 4: "k_grid_wavetiles", 5: "k_grid_stack"}
 
+# HBM traffic of one launch of the default gridder on this workload, from two rocprofv3
+# counter passes over this script (profiles/k_grid_wavetiles_mwa2048.md): FETCH_SIZE scaled
+# by 2.0 plus WRITE_SIZE scaled by 1.0, the factors a plain 1 GiB device copy reads on the
+# same counters. It describes the gridder sources it was taken on (SHA-256 over the files
+# below) and is reported only while they are unchanged.
+GRIDDER_SOURCES = ("paper_0902_0915_amd/csrc/gridder_core.h", "paper_0902_0915_amd/csrc/grid.hip",
+                   "paper_0902_0915_amd/csrc/plan.hip", "paper_0902_0915_amd/csrc/internal.h")
+MEASURED_TRAFFIC = {
+    "sha256": "ea012d08e98a30891fc47a3a5730d9c173d92595182087fc44978daacf15e53e",
+    "fetch_kib": 1.99e6, "write_kib": 1.7446e5, "fetch_scale": 2.0, "write_scale": 1.0,
+    "profile": "profiles/k_grid_wavetiles_mwa2048.md",
+}
+
+
+def gridder_traffic():
+    """Measured bytes per gridder launch, or None if the sources changed since."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in GRIDDER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    m = MEASURED_TRAFFIC
+    if h.hexdigest() != m["sha256"]:
+        return None
+    return int((m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024)
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -150,22 +176,31 @@ def main():
 
     nvis = info["nkept"] * wl.npol
     value = nvis / (wall_ms * 1e-3) / 1e6
-    # Algorithmic traffic of the gridder: every kept visibility read once (8 B per pol) and
-    # the grid written once (8 B per cell per pol). Flops: 49 taps x npol x complex-by-real
-    # FMA (4 flop) per kept group.
-    alg_bytes = info["nkept"] * wl.npol * 8 + wl.npol * wl.nx * wl.ny * 8
-    alg_flop = info["nkept"] * wl.W * wl.W * wl.npol * 4
-    tflops = alg_flop / (kern_ms * 1e-3) / 1e12
+    # Dominant kernel: the gridder. Its algorithmic bytes are the kept visibilities, each read
+    # once (8 B per polarisation); the grid write (8 B per cell per polarisation) belongs to
+    # the merge launch, and both together make one mw_grid call.
     kname = f"{KERNEL_NAMES.get(info['variant'], 'k_grid')}<{wl.npol},{wl.W}>"
-    roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": kname, "kernel_ms": round(kern_ms, 4),
-                "alg_flop_per_launch": alg_flop}
+    alg_bytes_kernel = nvis * 8
+    kern_gbs = alg_bytes_kernel / (kern_ms * 1e-3) / 1e9
+    traffic = gridder_traffic() if (info["variant"] == 4 and info["flush"] == 2 and not tuning) else None
+    roofline = {"bound": "hbm", "achieved": round(kern_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(kern_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                "kernel_ms": round(kern_ms, 4), "alg_bytes_per_launch": alg_bytes_kernel,
+                "traffic_profile": MEASURED_TRAFFIC["profile"] if traffic else None}
+    # The whole mw_grid call (gridder + merge) against HBM, and the step.
+    alg_bytes = nvis * 8 + wl.npol * wl.nx * wl.ny * 8
     step_gbs = alg_bytes / (wall_ms * 1e-3) / 1e9
     grid_gbs = alg_bytes / ((kern_ms + merge_ms) * 1e-3) / 1e9
     hbm = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "alg_bytes_per_grid": alg_bytes,
            "gridding_achieved": round(grid_gbs, 1), "gridding_frac": round(grid_gbs / HBM_PEAK_GBS, 4),
            "step_frac": round(step_gbs / HBM_PEAK_GBS, 4)}
+    # The same kernel against the FP32 vector peak: 49 taps x npol x complex-by-real FMA
+    # (4 flop) per kept group, the direct form's count.
+    alg_flop = info["nkept"] * wl.W * wl.W * wl.npol * 4
+    tflops = alg_flop / (kern_ms * 1e-3) / 1e12
+    alu = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+           "alg_flop_per_launch": alg_flop}
 
     batched = None
     if not args.no_batched:
@@ -186,7 +221,8 @@ def main():
                    "launch": {k: info[k] for k in ("tile", "split", "wg_waves", "order",
                                                    "variant", "flush", "schedule", "nwork")}},
         "roofline": roofline,
-        "hbm_roofline": hbm,
+        "grid_call_roofline": hbm,
+        "alu_roofline": alu,
         "grid_mvis_s": round(nvis / ((kern_ms + merge_ms) * 1e-3) / 1e6, 1),
         "merge_ms": round(merge_ms, 4),
         "step_event_ms": round(ev_ms, 4),
