@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmwagrid.so")
-SOURCES = ["abi.cpp", "pswf.cpp", "plan.hip", "grid.hip", "degrid.hip", "image.hip",
+SOURCES = ["abi.cpp", "pswf.cpp", "plan.hip", "grid.hip", "degrid.hip", "image.hip", "fft.hip",
            "stack.hip", "batched.hip", "tuner.cpp"]
 ARCH = os.environ.get("MWG_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -7,8 +7,10 @@
 //               with sign -i.
 // Centring uses the identity exp(2 pi i (g - n/2)(p - n/2)/n) =
 // (-1)^g (-1)^p (-1)^(n/2) exp(2 pi i g p/n): a checkerboard sign before and after an
-// ordinary unnormalised FFT, with the constant (-1)^((nx + ny)/2). The FFT itself is
-// rocFFT's single-precision in-place complex transform, batched over polarisations.
+// ordinary unnormalised FFT, with the constant (-1)^((nx + ny)/2). Power-of-two grids use
+// the library's own two-pass transform (fft.hip), which folds the signs and the correction
+// into its loads and stores. Other sizes use rocFFT's single-precision in-place complex
+// transform, batched over polarisations, between two scaling passes.
 #include "internal.h"
 
 #include <rocfft/rocfft.h>
@@ -103,6 +105,14 @@ void image_release(Instance &I) {
 
 Status launch_image(Instance &I, const float2 *in, float2 *out, int direction, int correct,
                     hipStream_t s) {
+    if (fft2d_supported(I.nx, I.ny)) {
+        if (!I.twx) {
+            MWG_TRY(fft2d_twiddles(I.arena, I.nx, &I.twx, s));
+            MWG_TRY(fft2d_twiddles(I.arena, I.ny, &I.twy, s));
+        }
+        return launch_fft2d(in, out, I.nx, I.ny, I.npol, I.twx, I.twy, (const float *)I.corrx,
+                            (const float *)I.corry, direction, correct, s);
+    }
     MWG_TRY(image_prepare(I));
     FftPlans *f = (FftPlans *)I.fft;
     const float gsign = (((I.nx + I.ny) / 2) & 1) ? -1.0f : 1.0f;

@@ -125,7 +125,8 @@ struct Instance {
     // host copies for export
     std::vector<float> h_tab, h_corrx, h_corry;
     // image plans (rocFFT); opaque here
-    void *fft = nullptr;
+    void *fft = nullptr;                          // rocFFT plans (grids of other sizes)
+    float2 *twx = nullptr, *twy = nullptr;        // two-pass transform twiddles (power-of-two grids)
 };
 
 struct Plan {
@@ -166,6 +167,11 @@ Status image_prepare(Instance &I);
 Status launch_image(Instance &I, const float2 *in, float2 *out, int direction, int correct,
                     hipStream_t s);
 void image_release(Instance &I);
+bool fft2d_supported(int nx, int ny);
+Status fft2d_twiddles(DevArena &arena, int n, float2 **out, hipStream_t s);
+Status launch_fft2d(const float2 *in, float2 *out, int nx, int ny, int npol, const float2 *twx,
+                    const float2 *twy, const float *corrx, const float *corry, int direction, int correct,
+                    hipStream_t st);
 Status launch_image_scale(const float2 *in, float2 *out, int nx, int ny, int npol,
                           const float *corrx, const float *corry, int checker, int divide,
                           hipStream_t s);

@@ -239,6 +239,25 @@ def test_image_parity_both_directions(mw, ny, nx, correct):
     assert np.array_equal(inplace, fwd)
 
 
+@pytest.mark.parametrize("ny,nx,npol", [(64, 4096, 1), (4096, 64, 1), (512, 256, 2), (2048, 2048, 4)])
+def test_image_two_pass_transform_shapes(mw, ny, nx, npol):
+    """Power-of-two grids use the library's two-pass transform: non-square shapes at both
+    ends of its size range and several polarisations, both directions, with and without
+    the correction, against the oracle."""
+    import dataclasses
+    rng = np.random.default_rng(nx * 3 + ny + npol)
+    wl = dataclasses.replace(synth.tiny(), nx=nx, ny=ny, npol=npol)
+    wl.du = synth.cell_size(wl.uvw, wl.freq, min(nx, ny))
+    wl.dv = wl.du
+    z = (rng.standard_normal((npol, ny, nx)) + 1j * rng.standard_normal((npol, ny, nx))).astype(np.complex64)
+    with _plan(mw, wl) as plan:
+        for correct in (False, True):
+            fwd = to_host(plan.image(to_dev(z), direction=1, correct=correct))
+            adj = to_host(plan.image(to_dev(z), direction=-1, correct=correct))
+            assert nl2(fwd, orc.image(z, W=7, correct=correct)) <= TOL, correct
+            assert nl2(adj, orc.image_adjoint(z, W=7, correct=correct)) <= TOL, correct
+
+
 @pytest.mark.parametrize("correct", [False])
 def test_autograd_matches_oracle_gradients(mw, correct):
     # The loss is taken on the dirty image without the correction: dividing by the kernel
