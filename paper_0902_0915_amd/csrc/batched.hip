@@ -3,8 +3,9 @@
 //
 // Gridding: one launch over the (instance, work item) pairs of all instances, one pair per
 // wavefront, in instance order; each item is gridded with the wave-tile body shared with
-// the single-instance gridder (gridder_core.h). Then one merge launch over
-// the cells of every instance's grid. Degridding: one launch over all instances' work items
+// the single-instance gridder (gridder_core.h). Then one merge launch over the cell blocks
+// of every instance's grid that some work item reaches, and one launch that writes zeros to
+// the other blocks, both over (instance, block) lists built with the plan. Degridding: one launch over all instances' work items
 // with the shared degrid body (degrid_core.h), after one prologue launch that zeroes the
 // outputs of dropped groups and the gain gradients.
 //
@@ -39,7 +40,8 @@ struct BatchDesc {
     const WorkItem *work;
     float *partial;
     const int32_t *tile_work, *work_ids;
-    int32_t nx, ny, ntx, nty, nwork, nant, ndropped, pad1;
+    const int32_t *mblocks; // merge blocks some work item reaches, then those none reaches
+    int32_t nx, ny, ntx, nty, nwork, nant, ndropped, n_mblocks;
 };
 
 struct BatchItem {
@@ -49,7 +51,7 @@ struct BatchItem {
 struct Batch {
     int ninst = 0, npol = 1, W = 7, O = 8, T = 8, waves = 8, STR = 0, PL = 0, nitems = 0;
     int grid_blocks = 0;     // gridder workgroups (waves of them, one work item per wave)
-    int64_t merge_blocks = 0, prologue_n = 0;
+    int64_t merge_blocks = 0, zero_blocks = 0, prologue_n = 0;
     int ant_in_lds = 0;
     size_t grid_lds = 0, degrid_lds = 0;
     DevArena arena;
@@ -57,7 +59,8 @@ struct Batch {
     hipEvent_t desc_ev = nullptr;
     bool desc_pending = false;
     BatchItem *d_items = nullptr;
-    int64_t *d_merge_start = nullptr, *d_pro_start = nullptr;
+    int64_t *d_pro_start = nullptr;
+    int2 *d_mpairs = nullptr; // (instance, block) of every merge block, then of every zero block
     const float *tab8 = nullptr;
     float tapk[16 * 8] = {0};
     hipStream_t cap = nullptr;
@@ -142,18 +145,35 @@ __device__ inline int find_inst(const int64_t *start, int n, int64_t b) {
     return lo;
 }
 
+// The merge pass over every instance's listed blocks that some work item reaches, one
+// (instance, block) pair of the concatenated list per workgroup.
 template <int NPOL>
-__global__ __launch_bounds__(kMergeB * kMergeB) void k_merge_batched(const BatchDesc *desc, const int64_t *start,
-                                                                     int ninst, int lgT, int W) {
+__global__ __launch_bounds__(kMergeB * kMergeB) void k_merge_batched(const BatchDesc *desc, const int2 *pairs,
+                                                                     int lgT, int W) {
     __shared__ int2 rng[kMergeTiles];
-    const int64_t b = blockIdx.x;
-    const int inst = find_inst(start, ninst, b);
-    const BatchDesc &d = desc[inst];
-    const int local = (int)(b - start[inst]);
+    const int h = (W - 1) / 2, tid = threadIdx.x;
+    const int2 pr = pairs[blockIdx.x];
+    const BatchDesc &d = desc[pr.x];
     const int bpr = (d.nx + kMergeB - 1) / kMergeB;
-    const int by = local / bpr, bx = local - by * bpr;
-    merge_block<NPOL>(d.grid, d.partial, d.tile_work, d.work_ids, d.nx, d.ny, lgT, d.ntx, d.nty, W,
-                      d.accumulate, bx * kMergeB, by * kMergeB, rng);
+    const int by = pr.y / bpr, bx = pr.y - by * bpr;
+    const int x0 = bx * kMergeB, y0 = by * kMergeB;
+    const MergeBounds m = merge_bounds(x0, y0, h, lgT, d.ntx, d.nty);
+    if (tid < 32) merge_stage(d.tile_work, d.ntx, m, tid, rng);
+    __syncthreads();
+    merge_cell<NPOL>(d.grid, d.partial, d.work_ids, d.nx, d.ny, lgT, W, d.accumulate, m, rng,
+                     x0 + (tid & (kMergeB - 1)), y0 + tid / kMergeB);
+}
+
+// Zeros of every instance's listed blocks that no work item reaches (nothing when
+// accumulating).
+template <int NPOL>
+__global__ __launch_bounds__(kMergeB * kMergeB) void k_zero_batched(const BatchDesc *desc, const int2 *pairs) {
+    const int2 pr = pairs[blockIdx.x];
+    const BatchDesc &d = desc[pr.x];
+    if (d.accumulate) return;
+    const int bpr = (d.nx + kMergeB - 1) / kMergeB;
+    const int by = pr.y / bpr, bx = pr.y - by * bpr;
+    zero_block<NPOL>(d.grid, d.nx, d.ny, bx * kMergeB, by * kMergeB);
 }
 
 // Zeroes the adjoint outputs of dropped groups (entries [0, start[ninst]) of the dropped
@@ -231,9 +251,16 @@ Status enqueue_grid(Batch &B, hipStream_t s) {
     default: return make_error(MW_ERR_UNSUPPORTED, "batched gridder needs W in {3, 5, 7}");
     }
     MWG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_merge_batched<NPOL>, dim3((unsigned)B.merge_blocks), dim3(kMergeB * kMergeB), 0, s,
-                       B.d_desc, (const int64_t *)B.d_merge_start, B.ninst, ilog2(B.T), B.W);
-    MWG_HIP(hipGetLastError());
+    if (B.merge_blocks > 0) {
+        hipLaunchKernelGGL(k_merge_batched<NPOL>, dim3((unsigned)B.merge_blocks), dim3(kMergeB * kMergeB), 0, s,
+                           B.d_desc, (const int2 *)B.d_mpairs, ilog2(B.T), B.W);
+        MWG_HIP(hipGetLastError());
+    }
+    if (B.zero_blocks > 0) {
+        hipLaunchKernelGGL(k_zero_batched<NPOL>, dim3((unsigned)B.zero_blocks), dim3(kMergeB * kMergeB), 0, s,
+                           B.d_desc, (const int2 *)B.d_mpairs + B.merge_blocks);
+        MWG_HIP(hipGetLastError());
+    }
     return Status::Ok();
 }
 
@@ -342,7 +369,7 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     // descriptors (fixed part)
     std::vector<BatchDesc> desc(B->ninst);
     std::vector<BatchItem> items;
-    std::vector<int64_t> mstart(B->ninst + 1, 0), pstart(2 * B->ninst + 1, 0);
+    std::vector<int64_t> mstart(B->ninst + 1, 0), zstart(B->ninst + 1, 0), pstart(2 * B->ninst + 1, 0);
     int max_nant = 0;
     for (int i = 0; i < B->ninst; i++) {
         Instance &I = *P.inst[i];
@@ -360,6 +387,8 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         d.partial = I.partial;
         d.tile_work = I.tile_work;
         d.work_ids = I.work_ids;
+        d.mblocks = I.mblocks;
+        d.n_mblocks = I.n_mblocks;
         d.nx = I.nx;
         d.ny = I.ny;
         d.ntx = I.ntx;
@@ -369,7 +398,8 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         d.ndropped = (int)(I.ngroups - I.nkept);
         max_nant = std::max(max_nant, I.nant);
         for (int w = 0; w < I.nwork; w++) items.push_back({i, w});
-        mstart[i + 1] = mstart[i] + (int64_t)((I.ny + kMergeB - 1) / kMergeB) * ((I.nx + kMergeB - 1) / kMergeB);
+        mstart[i + 1] = mstart[i] + I.n_mblocks;
+        zstart[i + 1] = zstart[i] + I.n_zblocks;
         pstart[i + 1] = pstart[i] + d.ndropped;
     }
     // second half: gain-gradient entries, numbered after all dropped entries
@@ -381,6 +411,7 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     // gathers over every instance at once and runs ~4x slower.
     B->nitems = (int)items.size();
     B->merge_blocks = mstart[B->ninst];
+    B->zero_blocks = zstart[B->ninst];
     void *p;
     MWG_TRY(B->arena.alloc(&p, sizeof(BatchDesc) * B->ninst));
     B->d_desc = (BatchDesc *)p;
@@ -394,9 +425,25 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     B->d_items = (BatchItem *)p;
     if (!items.empty())
         MWG_HIP(hipMemcpy(B->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
-    MWG_TRY(B->arena.alloc(&p, sizeof(int64_t) * mstart.size()));
-    B->d_merge_start = (int64_t *)p;
-    MWG_HIP(hipMemcpy(B->d_merge_start, mstart.data(), sizeof(int64_t) * mstart.size(), hipMemcpyHostToDevice));
+    {
+        // (instance, block) pairs: all merge blocks, then all zero blocks
+        std::vector<int2> mp;
+        mp.reserve((size_t)(B->merge_blocks + B->zero_blocks));
+        std::vector<std::vector<int32_t>> lists(B->ninst);
+        for (int i = 0; i < B->ninst; i++) {
+            const Instance &I = *P.inst[i];
+            lists[i].resize((size_t)(I.n_mblocks + I.n_zblocks));
+            if (!lists[i].empty())
+                MWG_HIP(hipMemcpy(lists[i].data(), I.mblocks, 4 * lists[i].size(), hipMemcpyDeviceToHost));
+            for (int k = 0; k < I.n_mblocks; k++) mp.push_back(make_int2(i, lists[i][k]));
+        }
+        for (int i = 0; i < B->ninst; i++)
+            for (int k = P.inst[i]->n_mblocks; k < (int)lists[i].size(); k++) mp.push_back(make_int2(i, lists[i][k]));
+        MWG_TRY(B->arena.alloc(&p, sizeof(int2) * std::max<size_t>(mp.size(), 1)));
+        B->d_mpairs = (int2 *)p;
+        if (!mp.empty())
+            MWG_HIP(hipMemcpy(B->d_mpairs, mp.data(), sizeof(int2) * mp.size(), hipMemcpyHostToDevice));
+    }
     MWG_TRY(B->arena.alloc(&p, sizeof(int64_t) * pstart.size()));
     B->d_pro_start = (int64_t *)p;
     MWG_HIP(hipMemcpy(B->d_pro_start, pstart.data(), sizeof(int64_t) * pstart.size(), hipMemcpyHostToDevice));

@@ -462,14 +462,31 @@ __global__ __launch_bounds__(1024) void k_grid_scatter(GridArgs a, int flush) {
 
 // Merge pass of flush 2: every grid cell sums the partial tiles of all work items whose
 // (haloed) tile covers it, in a fixed order.
+// The merge pass over the listed blocks that some work item reaches, one per workgroup.
 template <int NPOL>
 __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const float *partial,
                                                               const int32_t *tile_work, const int32_t *work_ids,
-                                                              int nx, int ny, int lgT, int ntx, int nty, int W,
-                                                              int accumulate) {
+                                                              const int32_t *blocks, int nx, int ny, int lgT,
+                                                              int ntx, int nty, int W, int accumulate) {
     __shared__ int2 rng[kMergeTiles];
-    merge_block<NPOL>(grid, partial, tile_work, work_ids, nx, ny, lgT, ntx, nty, W, accumulate,
-                      blockIdx.x * kMergeB, blockIdx.y * kMergeB, rng);
+    const int bpr = (nx + kMergeB - 1) / kMergeB, h = (W - 1) / 2;
+    const int tid = threadIdx.x;
+    const int b = blocks[blockIdx.x], by = b / bpr, bx = b - by * bpr;
+    const int x0 = bx * kMergeB, y0 = by * kMergeB;
+    const MergeBounds m = merge_bounds(x0, y0, h, lgT, ntx, nty);
+    if (tid < 32) merge_stage(tile_work, ntx, m, tid, rng);
+    __syncthreads();
+    merge_cell<NPOL>(grid, partial, work_ids, nx, ny, lgT, W, accumulate, m, rng, x0 + (tid & (kMergeB - 1)),
+                     y0 + tid / kMergeB);
+}
+
+// Zeros of the listed blocks that no work item reaches, one per workgroup.
+template <int NPOL>
+__global__ __launch_bounds__(kMergeB * kMergeB) void k_zero_blocks(float2 *grid, const int32_t *blocks, int nx,
+                                                                    int ny) {
+    const int bpr = (nx + kMergeB - 1) / kMergeB;
+    const int b = blocks[blockIdx.x], by = b / bpr, bx = b - by * bpr;
+    zero_block<NPOL>(grid, nx, ny, bx * kMergeB, by * kMergeB);
 }
 
 template <int NPOL>
@@ -521,11 +538,18 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
     }
     if (I.timing) MWG_HIP(hipEventRecord(I.tev[1], s));
     if (flush == 2) {
-        dim3 blk(kMergeB * kMergeB), grd((I.nx + kMergeB - 1) / kMergeB, (I.ny + kMergeB - 1) / kMergeB);
-        hipLaunchKernelGGL(k_merge<NPOL>, grd, blk, 0, s, a.grid, (const float *)I.partial,
-                           (const int32_t *)I.tile_work, (const int32_t *)I.work_ids, I.nx, I.ny,
-                           ilog2(L.tile), I.ntx, I.nty, I.W, accumulate);
-        MWG_HIP(hipGetLastError());
+        if (I.n_mblocks > 0) {
+            hipLaunchKernelGGL(k_merge<NPOL>, dim3(I.n_mblocks), dim3(kMergeB * kMergeB), 0, s, a.grid,
+                               (const float *)I.partial, (const int32_t *)I.tile_work, (const int32_t *)I.work_ids,
+                               (const int32_t *)I.mblocks, I.nx, I.ny, ilog2(L.tile), I.ntx, I.nty, I.W,
+                               accumulate);
+            MWG_HIP(hipGetLastError());
+        }
+        if (I.n_zblocks > 0 && !accumulate) {
+            hipLaunchKernelGGL(k_zero_blocks<NPOL>, dim3(I.n_zblocks), dim3(kMergeB * kMergeB), 0, s, a.grid,
+                               (const int32_t *)I.mblocks + I.n_mblocks, I.nx, I.ny);
+            MWG_HIP(hipGetLastError());
+        }
     }
     if (I.timing) {
         MWG_HIP(hipEventRecord(I.tev[2], s));

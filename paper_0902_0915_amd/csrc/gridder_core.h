@@ -245,57 +245,62 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
     }
 }
 
-// The merge pass over one block of kMergeB x kMergeB cells, run by kMergeB^2 threads (one
-// cell each). Every cell is the sum over the partial tiles of the work items whose haloed
-// tile covers it, in a fixed order (tile row, tile column, then the tile's work items), so
-// the result is bit-reproducible. The work-item ranges of the tiles that can cover the
-// block are staged in LDS first: a span of 16 + 2h cells meets at most
-// floor((15 + 2h) / T) + 2 tiles per axis, which is 5 for T >= 8 and h <= 7 (W <= 15). A
-// block that no work item reaches is written as zeros (or left alone when accumulating).
-constexpr int kMergeB = 16;
-constexpr int kMergeTiles = 25;
+// The merge pass over blocks of kMergeB x kMergeB cells, one cell per thread. Every cell is
+// the sum over the partial tiles of the work items whose haloed tile covers it, in a fixed
+// order (tile row, tile column, then the tile's work items), so the result is
+// bit-reproducible. The work-item ranges of the tiles that can cover a block are staged in
+// LDS first: a span of 16 + 2h cells meets at most floor((15 + 2h) / T) + 2 tiles per axis,
+// which is 5 for T >= 8 and h <= 7 (W <= 15) (a kMergeTiles table). Only blocks that some
+// work item reaches are listed for the merge; the plan lists the others apart and a plain
+// fill writes their zeros.
+
+struct MergeBounds {
+    int tx_lo, ty_lo, ntxb, ntyb;
+};
+
+__device__ inline MergeBounds merge_bounds(int x0, int y0, int h, int lgT, int ntx, int nty) {
+    MergeBounds m;
+    m.tx_lo = max(0, x0 - h) >> lgT;
+    m.ty_lo = max(0, y0 - h) >> lgT;
+    m.ntxb = min(ntx - 1, (x0 + kMergeB - 1 + h) >> lgT) - m.tx_lo + 1;
+    m.ntyb = min(nty - 1, (y0 + kMergeB - 1 + h) >> lgT) - m.ty_lo + 1;
+    return m;
+}
+
+// Entry e of block (x0, y0)'s tile-range table.
+__device__ inline void merge_stage(const int32_t *tile_work, int ntx, const MergeBounds &m, int e, int2 *rng) {
+    if (e < m.ntxb * m.ntyb) {
+        const int t = (m.ty_lo + e / m.ntxb) * ntx + m.tx_lo + e % m.ntxb;
+        rng[e] = make_int2(tile_work[t], tile_work[t + 1]);
+    }
+}
 
 template <int NPOL>
-__device__ inline void merge_block(float2 *grid, const float *partial, const int32_t *tile_work,
-                                   const int32_t *work_ids, int nx, int ny, int lgT, int ntx, int nty,
-                                   int W, int accumulate, int x0, int y0, int2 *rng) {
+__device__ inline void merge_cell(float2 *grid, const float *partial, const int32_t *work_ids, int nx, int ny,
+                                  int lgT, int W, int accumulate, const MergeBounds &m, const int2 *rng,
+                                  int x, int y) {
     constexpr int NC = 2 * NPOL;
     const int T = 1 << lgT, h = (W - 1) / 2, R = T + W - 1;
-    const int tid = threadIdx.x;
-    const int tx_lo = max(0, x0 - h) >> lgT, tx_hi = min(ntx - 1, (x0 + kMergeB - 1 + h) >> lgT);
-    const int ty_lo = max(0, y0 - h) >> lgT, ty_hi = min(nty - 1, (y0 + kMergeB - 1 + h) >> lgT);
-    const int ntxb = tx_hi - tx_lo + 1, ntyb = ty_hi - ty_lo + 1;
-    if (tid < ntxb * ntyb) {
-        const int t = (ty_lo + tid / ntxb) * ntx + tx_lo + tid % ntxb;
-        rng[tid] = make_int2(tile_work[t], tile_work[t + 1]);
-    }
-    __syncthreads();
-    int total = 0;
-    for (int i = 0; i < ntxb * ntyb; i++) total += rng[i].y - rng[i].x;
-    const int x = x0 + (tid & (kMergeB - 1)), y = y0 + tid / kMergeB;
     if (x >= nx || y >= ny) return;
-    if (total == 0 && accumulate) return;
     float acc[NC];
 #pragma unroll
     for (int q = 0; q < NC; q++) acc[q] = 0.0f;
-    if (total > 0) {
-        const int txc = x >> lgT, tyc = y >> lgT;
-        for (int dy = -1; dy <= 1; dy++) {
-            const int tty = tyc + dy;
-            if (tty < ty_lo || tty > ty_hi) continue;
-            const int r = y - (tty * T - h);
-            if (r < 0 || r >= R) continue;
-            for (int dx = -1; dx <= 1; dx++) {
-                const int ttx = txc + dx;
-                if (ttx < tx_lo || ttx > tx_hi) continue;
-                const int c = x - (ttx * T - h);
-                if (c < 0 || c >= R) continue;
-                const int2 rg = rng[(tty - ty_lo) * ntxb + (ttx - tx_lo)];
-                for (int k = rg.x; k < rg.y; k++) {
-                    const float *src = partial + (int64_t)work_ids[k] * NC * R * R + r * R + c;
+    const int txc = x >> lgT, tyc = y >> lgT;
+    for (int dy = -1; dy <= 1; dy++) {
+        const int tty = tyc + dy;
+        if (tty < m.ty_lo || tty >= m.ty_lo + m.ntyb) continue;
+        const int r = y - (tty * T - h);
+        if (r < 0 || r >= R) continue;
+        for (int dx = -1; dx <= 1; dx++) {
+            const int ttx = txc + dx;
+            if (ttx < m.tx_lo || ttx >= m.tx_lo + m.ntxb) continue;
+            const int c = x - (ttx * T - h);
+            if (c < 0 || c >= R) continue;
+            const int2 rg = rng[(tty - m.ty_lo) * m.ntxb + (ttx - m.tx_lo)];
+            for (int k = rg.x; k < rg.y; k++) {
+                const float *src = partial + (int64_t)work_ids[k] * NC * R * R + r * R + c;
 #pragma unroll
-                    for (int q = 0; q < NC; q++) acc[q] += src[(int64_t)q * R * R];
-                }
+                for (int q = 0; q < NC; q++) acc[q] += src[(int64_t)q * R * R];
             }
         }
     }
@@ -310,6 +315,15 @@ __device__ inline void merge_block(float2 *grid, const float *partial, const int
         }
         *dst = v;
     }
+}
+
+// Zeros of one merge block (the NPOL planes of its cells), kMergeB^2 threads.
+template <int NPOL>
+__device__ inline void zero_block(float2 *grid, int nx, int ny, int x0, int y0) {
+    const int x = x0 + (threadIdx.x & (kMergeB - 1)), y = y0 + threadIdx.x / kMergeB;
+    if (x >= nx || y >= ny) return;
+#pragma unroll
+    for (int p = 0; p < NPOL; p++) grid[((int64_t)p * ny + y) * nx + x] = make_float2(0.f, 0.f);
 }
 
 } // namespace mwg

@@ -52,6 +52,11 @@ inline int ilog2(int v) {
     return r;
 }
 
+// Merge pass: blocks of kMergeB x kMergeB cells; a block meets at most kMergeTiles tiles
+// (5 x 5 for tiles of 8 or more cells and supports up to 15).
+constexpr int kMergeB = 16;
+constexpr int kMergeTiles = 25;
+
 // Packed per-group position: cx | cy << 12 | (px + O/2) << 24 | (py + O/2) << 28.
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 __host__ __device__ inline uint32_t pack_pos(int cx, int cy, int pxo, int pyo) {
@@ -111,6 +116,9 @@ struct Instance {
     WorkItem *work = nullptr;     // [nwork]
     int32_t *tile_work = nullptr; // [ntiles + 1] CSR: work items of each tile (merge flush)
     int32_t *work_ids = nullptr;  // [nwork] work item ids grouped by tile
+    int32_t *mblocks = nullptr;   // merge blocks (by * bpr + bx): those some work item reaches,
+    int n_mblocks = 0;            //   then the n_zblocks that none reaches (written as zeros)
+    int n_zblocks = 0;
     float *partial = nullptr;     // merge flush scratch: [nwork][2*npol][R*R]
     size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)

@@ -530,6 +530,30 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         std::vector<int32_t> fillp(tw.begin(), tw.end() - 1);
         for (size_t i = 0; i < items.size(); i++) ids[fillp[items[i].tile]++] = (int32_t)i;
     }
+    // Merge blocks that some work item's haloed tile reaches, then those none reaches.
+    std::vector<int32_t> mlist;
+    int nmerge = 0;
+    {
+        const int bpr = (I.nx + kMergeB - 1) / kMergeB, bpc = (I.ny + kMergeB - 1) / kMergeB;
+        const int h = (I.W - 1) / 2;
+        std::vector<int32_t> zero;
+        mlist.reserve((size_t)bpr * bpc);
+        for (int by = 0; by < bpc; by++)
+            for (int bx = 0; bx < bpr; bx++) {
+                const int x0 = bx * kMergeB, y0 = by * kMergeB;
+                const int tx_lo = std::max(0, x0 - h) >> tb, tx_hi = std::min(ntx - 1, (x0 + kMergeB - 1 + h) >> tb);
+                const int ty_lo = std::max(0, y0 - h) >> tb, ty_hi = std::min(nty - 1, (y0 + kMergeB - 1 + h) >> tb);
+                bool any = false;
+                for (int ty = ty_lo; ty <= ty_hi && !any; ty++)
+                    for (int tx = tx_lo; tx <= tx_hi && !any; tx++) {
+                        const int64_t t = (int64_t)ty * ntx + tx;
+                        any = tw[t + 1] > tw[t];
+                    }
+                (any ? mlist : zero).push_back(by * bpr + bx);
+            }
+        nmerge = (int)mlist.size();
+        mlist.insert(mlist.end(), zero.begin(), zero.end());
+    }
     // (re)allocate schedule arrays: these are small; keep them in the arena
     I.L = L;
     I.ntx = ntx;
@@ -557,6 +581,13 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     MWG_HIP(hipMemcpyAsync(I.tile_work, tw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
     if (!ids.empty())
         MWG_HIP(hipMemcpyAsync(I.work_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
+    if (!I.mblocks) { // the block count depends only on the grid size
+        MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(mlist.size(), 1)));
+        I.mblocks = (int32_t *)p;
+    }
+    MWG_HIP(hipMemcpyAsync(I.mblocks, mlist.data(), 4 * mlist.size(), hipMemcpyHostToDevice, s));
+    I.n_mblocks = nmerge;
+    I.n_zblocks = (int)mlist.size() - nmerge;
     // Sorted per-group arrays follow the new permutation.
     if (nk > 0) {
         if (resort) {
