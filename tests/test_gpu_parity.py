@@ -193,6 +193,28 @@ def test_degrid_parity_and_adjoint(mw, small_mwa, tuning):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
+@pytest.mark.parametrize("npol,W,weighted", [(1, 7, True), (2, 5, False), (4, 3, True), (2, 7, True), (1, 3, False)])
+def test_degrid_without_gains_all_lane_layouts(mw, npol, W, weighted):
+    """The gains-free degridder (one wavefront per work item, factorised gather) for every
+    lane layout (1, 2 or 4 polarisations) and support, with weights and flagged groups."""
+    rng = np.random.default_rng(100 * npol + W)
+    wl = synth.mwa_scale(seed=2007, nant=48, nchan=8, ntime=2, npol=npol, n=256, nsrc=10, W=W, make_vis=False)
+    wl.flags = (rng.random(wl.ngroups) < 0.1).astype(np.uint8)
+    w64 = rng.uniform(0.5, 1.5, wl.ngroups) if weighted else None
+    if weighted:
+        wl.weights = w64.astype(np.float32)
+    G = (rng.standard_normal((npol, wl.ny, wl.nx)) + 1j * rng.standard_normal((npol, wl.ny, wl.nx)))
+    G = G.astype(np.complex64)
+    pos, keep, _ = oracle_positions(wl, weights=w64)
+    ref = orc.degrid(pos, keep, G, W, wl.O, nchan=wl.nchan, weights=w64)
+    with _plan(mw, wl, with_ants=False) as plan:
+        info = plan.info(0)
+        got = to_host(plan.degrid(to_dev(G)))
+    assert info["variant"] == 4
+    assert nl2(got, ref) <= TOL
+    assert np.all(got[~keep] == 0)
+
+
 def test_degrid_gains_and_grad_gains(mw):
     rng = np.random.default_rng(11)
     wl = synth.mwa_scale(seed=2004, nant=40, nchan=4, ntime=2, npol=2, n=256, nsrc=10)
