@@ -175,6 +175,65 @@ def degrid(pos, keep, grid_, W, O, nchan=1, weights=None, gains=None, ant1=None,
     return out
 
 
+def grid_cells(pos, keep, vis, cells, nx, W, O, weights=None, table=None):
+    """Selected cells of ``grid`` (no gains), each summed directly from its definition
+    (Section 2.1, the convolution onto the grid read one output at a time): for cell (x, y)
+    and polarisation p, the sum over the kept groups centred at (x - t + h, y - s + h),
+    0 <= s, t < W, of T[py][s] T[px][t] w V[p]. For checks at sizes where the whole grid is
+    too large for the oracle; ``cells`` is int [k, 2] of (x, y). Returns complex128 [npol, k].
+    """
+    h = (W - 1) // 2
+    T = kernel_table(W, O) if table is None else np.asarray(table, dtype=np.float64)
+    pos = np.asarray(pos)
+    V = np.asarray(vis, dtype=np.complex128)
+    if V.ndim == 1:
+        V = V[:, None]
+    w_all = None if weights is None else np.asarray(weights, dtype=np.float64)
+    idx = np.flatnonzero(np.asarray(keep, dtype=bool))
+    key = pos[idx, 1].astype(np.int64) * nx + pos[idx, 0]
+    order = np.argsort(key, kind="stable")
+    idx, key = idx[order], key[order]
+    out = np.zeros((V.shape[1], len(cells)), dtype=np.complex128)
+    for k, (x, y) in enumerate(np.asarray(cells, dtype=np.int64)):
+        for s in range(W):
+            cy = y - s + h
+            if cy < 0:
+                continue
+            for t in range(W):
+                cx = x - t + h
+                if cx < 0 or cx >= nx:
+                    continue
+                lo, hi = np.searchsorted(key, [cy * nx + cx, cy * nx + cx + 1])
+                if hi == lo:
+                    continue
+                g = idx[lo:hi]
+                taps = T[pos[g, 3] + O // 2, s] * T[pos[g, 2] + O // 2, t]
+                if w_all is not None:
+                    taps = taps * w_all[g]
+                out[:, k] += taps @ V[g]
+    return out
+
+
+def degrid_groups(pos, grid_, groups, W, O, weights=None, table=None):
+    """Selected kept groups of ``degrid`` (no gains), each summed directly: y[p] =
+    w sum_{s,t} T[py][s] T[px][t] G[p][cy - h + s][cx - h + t]. Returns complex128
+    [len(groups), npol]."""
+    h = (W - 1) // 2
+    T = kernel_table(W, O) if table is None else np.asarray(table, dtype=np.float64)
+    G = np.asarray(grid_, dtype=np.complex128)
+    pos = np.asarray(pos)
+    g = np.asarray(groups, dtype=np.int64)
+    cx, cy, px, py = (pos[g, i].astype(np.int64) for i in range(4))
+    out = np.zeros((len(g), G.shape[0]), dtype=np.complex128)
+    for s in range(W):
+        for t in range(W):
+            taps = T[py + O // 2, s] * T[px + O // 2, t]
+            out += taps[:, None] * G[:, cy - h + s, cx - h + t].T
+    if weights is not None:
+        out *= np.asarray(weights, dtype=np.float64)[g][:, None]
+    return out
+
+
 def grid_stack(pos, keep, vis, nx, ny, O, kstack, koffset, ksupport, kidx, nchan=1,
                weights=None, gains=None, ant1=None, ant2=None, out=None, nthreads=None):
     """Kernel-stack gridding: complex tap K_k[py][px][s][t] of the group's kernel k."""
