@@ -63,6 +63,7 @@ struct GridArgs {
     // schedule 2: logical workgroup ranges per XCD (hardware workgroup h runs on XCD h % 8)
     int xcd_start[9];
     int schedule;
+    const int2 *coop;  // schedule 3: wave slots
 };
 
 // LDS layout of a tile: 2*NPOL planes (re, im of each polarisation), each R rows of STR
@@ -423,6 +424,81 @@ __global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, 
     wavetile_item<NPOL, W>(c, lane);
 }
 
+// Schedule 3 of variant 4: the waves of a workgroup share its items. Slot j of the
+// workgroup (wave j) grids part k of the nsub equal parts of item coop[j].x into its private
+// tile; after a barrier the workgroup sums each item's nsub tiles in wave order into the
+// item's partial slice. The waves of one item work on neighbouring cell rows of the same tile
+// at the same time, so a visibility line that feeds cells in several rows is fetched once
+// into the cache for all of them rather than once per cell row.
+template <int NPOL, int W>
+__global__ __launch_bounds__(1024) void k_grid_wavetiles_coop(GridArgs a) {
+    constexpr int NC = 2 * NPOL;
+    extern __shared__ __align__(16) float smem[];
+    const int nthreads = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = nthreads >> 6;
+    const int ntab = a.O * 8;
+    float *ltab = smem;
+    for (int i = tid; i < ntab; i += nthreads) ltab[i] = a.tab8[i];
+    const int R = a.T + W - 1;
+    const int per_wave = wavetile_per_wave(NC, a.plane);
+    float *mytile = smem + ntab + wave * per_wave + kStageFloats;
+    for (int i = lane; i < NC * a.plane; i += 64) mytile[i] = 0.0f;
+    __syncthreads();
+    const int2 *slots = a.coop + (int64_t)blockIdx.x * nwaves;
+    const int2 task = slots[wave];
+    const int item = __builtin_amdgcn_readfirstlane(task.x);
+    if (item >= 0) {
+        const int k = __builtin_amdgcn_readfirstlane(task.y & 0xFF);
+        const int nsub = __builtin_amdgcn_readfirstlane(task.y >> 8);
+        const WorkItem wk = a.work[item];
+        const int64_t n = (int64_t)wk.end - wk.begin;
+        ItemCtx c;
+        c.sv = smem + ntab + wave * per_wave;
+        c.tile = mytile;
+        c.vis = a.vis;
+        c.gains = a.gains;
+        c.perm = a.perm;
+        c.scode = a.scode;
+        c.sant = a.sant;
+        c.sw = a.sw;
+        c.tapk = a.tapk;
+        c.ltab = ltab;
+        c.grid = a.grid;
+        c.partial = nullptr;
+        c.wb = __builtin_amdgcn_readfirstlane((int)(wk.begin + n * k / nsub));
+        c.we = __builtin_amdgcn_readfirstlane((int)(wk.begin + n * (k + 1) / nsub));
+        c.tx0 = (wk.tile % a.ntx) * a.T;
+        c.ty0 = (wk.tile / a.ntx) * a.T;
+        c.T = a.T;
+        c.STR = a.str;
+        c.PL = a.plane;
+        c.nx = a.nx;
+        c.ny = a.ny;
+        c.flush = 0;
+        wavetile_item<NPOL, W>(c, lane);
+    }
+    __syncthreads();
+    // every item of the workgroup: its first wave's slot says how many tiles to sum
+    const int RR = R * R;
+    for (int j = 0; j < nwaves; j++) {
+        const int2 tj = slots[j];
+        const int it = __builtin_amdgcn_readfirstlane(tj.x);
+        if (it < 0 || (tj.y & 0xFF) != 0) continue;
+        const int nsub = __builtin_amdgcn_readfirstlane(tj.y >> 8);
+        const float *t0 = smem + ntab + j * per_wave + kStageFloats;
+        float *out = a.partial + (int64_t)it * NC * RR;
+        for (int idx = tid; idx < NC * RR; idx += nthreads) {
+            const int q = idx / RR, rr = idx - q * RR;
+            const int r = rr / R, col = rr - r * R;
+            const int off = q * a.plane + r * a.str + col;
+            float v = t0[off];
+            for (int m = 1; m < nsub; m++) v += t0[m * per_wave + off];
+            out[idx] = v;
+        }
+    }
+}
+
 template <int NPOL>
 __global__ __launch_bounds__(1024) void k_grid_scatter(GridArgs a, int flush) {
     extern __shared__ __align__(16) float smem[];
@@ -525,15 +601,26 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
         } else if (L.variant == 4) {
             const size_t lds = wavetiles_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
-            const dim3 g(L.schedule == 2 ? 8 * I.xcd_wgs : (I.nwork + L.wg_waves - 1) / L.wg_waves),
-                b(64 * L.wg_waves);
-            a.schedule = L.schedule;
-            for (int x = 0; x < 9; x++) a.xcd_start[x] = I.xcd_start[x];
-            switch (I.W) {
-            case 3: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 3>), g, b, lds, s, a, flush, I.nwork); break;
-            case 5: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 5>), g, b, lds, s, a, flush, I.nwork); break;
-            case 7: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 7>), g, b, lds, s, a, flush, I.nwork); break;
-            default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
+            if (L.schedule == 3) {
+                a.coop = I.coop;
+                const dim3 g(I.coop_wgs), b(64 * L.wg_waves);
+                switch (I.W) {
+                case 3: hipLaunchKernelGGL((k_grid_wavetiles_coop<NPOL, 3>), g, b, lds, s, a); break;
+                case 5: hipLaunchKernelGGL((k_grid_wavetiles_coop<NPOL, 5>), g, b, lds, s, a); break;
+                case 7: hipLaunchKernelGGL((k_grid_wavetiles_coop<NPOL, 7>), g, b, lds, s, a); break;
+                default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
+                }
+            } else {
+                const dim3 g(L.schedule == 2 ? 8 * I.xcd_wgs : (I.nwork + L.wg_waves - 1) / L.wg_waves),
+                    b(64 * L.wg_waves);
+                a.schedule = L.schedule;
+                for (int x = 0; x < 9; x++) a.xcd_start[x] = I.xcd_start[x];
+                switch (I.W) {
+                case 3: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 3>), g, b, lds, s, a, flush, I.nwork); break;
+                case 5: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 5>), g, b, lds, s, a, flush, I.nwork); break;
+                case 7: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 7>), g, b, lds, s, a, flush, I.nwork); break;
+                default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
+                }
             }
         } else {
             const size_t lds = scatter_lds(NPOL, L.tile, I.W, I.O);

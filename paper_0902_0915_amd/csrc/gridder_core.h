@@ -64,9 +64,11 @@ __device__ inline void wave_tile_add(float *p, int STR, int sg, const float (&ac
 }
 
 // Per-wave staging area of the wave-tile gridder: 32 groups at a time, each as its 2 * npol
-// visibility components (slots 0..7) and its column-tap row T[px][0..7] (slots 8..15).
+// visibility components (slots 0..7) and its column-tap row T[px][0..7] (slots 8..15), at a
+// stride of 20 floats: the 16-byte stores of 8 consecutive groups then cover all 32 banks
+// once (a stride of 16 would put every other group on the same 4 banks).
 constexpr int kStageGroups = 32;
-constexpr int kStageStride = 16;
+constexpr int kStageStride = 20;
 constexpr int kStageFloats = kStageGroups * kStageStride;
 
 // LDS floats per wave of the wave-tile gridder: the staging area, then the tile (NC planes
@@ -74,7 +76,8 @@ constexpr int kStageFloats = kStageGroups * kStageStride;
 __host__ __device__ inline int wavetile_per_wave(int nc, int pl) { return kStageFloats + ((nc * pl + 3) & ~3); }
 
 // Grids work item c with this wavefront (lanes as in variant 2) into its private tile and
-// writes the tile out. The tile must be zero on entry.
+// writes the tile out (flush 1: atomic adds into the grid, 2: the item's partial slice; 0:
+// the tile stays in LDS for the caller). The tile must be zero on entry.
 //
 // The groups of an item arrive sorted by centre cell and, within a cell, by the row
 // sub-position py. The separable tap factorises the work: for a run of groups with the same
@@ -235,7 +238,7 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
                 if (im != 0.0f) atomicAdd(dst + 1, im);
             }
         }
-    } else {
+    } else if (c.flush == 2) {
         float *out = c.partial;
         for (int idx = lane; idx < R * R; idx += 64) {
             const int r = idx / R, col = idx - r * R;

@@ -71,7 +71,7 @@ struct Launch {
     int order = 1;     // 1 cell-sorted, 2 input order within tile
     int variant = 1;   // gridder variant
     int flush = 1;     // 1 atomic, 2 deterministic merge
-    int schedule = 1;  // 1 largest first, 2 Z-order chunks per XCD
+    int schedule = 1;  // 1 largest first, 2 Z-order chunks per XCD, 3 workgroup-cooperative items
 };
 
 struct WorkItem {
@@ -100,6 +100,8 @@ struct Instance {
     bool timed = false;
     int xcd_start[9] = {0};   // schedule 2: first logical workgroup of each XCD's chunk
     int xcd_wgs = 0;          // schedule 2: workgroups per XCD in the launch grid
+    int coop_wgs = 0;         // schedule 3: workgroups in the launch grid
+    size_t cap_coop = 0;      // schedule 3: capacity of coop (wave slots)
     // device arrays (owned by arena)
     DevArena arena;
     uint32_t *pos = nullptr;      // [ngroups] packed, original order
@@ -114,6 +116,8 @@ struct Instance {
     uint32_t *ant_orig = nullptr; // [nrow] ant1 | ant2 << 16 (or null)
     int32_t *kidx_orig = nullptr; // [ngroups] kernel index (stacks)
     WorkItem *work = nullptr;     // [nwork]
+    int2 *coop = nullptr;         // schedule 3: [coop_wgs * wg_waves] per wave slot: (item or -1,
+                                  //   k | nsub << 8), wave k of the nsub consecutive waves of item
     int32_t *tile_work = nullptr; // [ntiles + 1] CSR: work items of each tile (merge flush)
     int32_t *work_ids = nullptr;  // [nwork] work item ids grouped by tile
     int32_t *mblocks = nullptr;   // merge blocks (by * bpr + bx): those some work item reaches,

@@ -522,6 +522,23 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         }
         I.xcd_wgs = maxlen;
     }
+    // Schedule 3: an item of n groups is shared by nsub = 2^k >= n / (split / wg_waves)
+    // (at most wg_waves) consecutive waves of one workgroup, wave j taking the j-th of nsub
+    // equal parts. Items are in largest-first order, so nsub never grows along the list and
+    // the items pack the workgroups' wave slots without gaps (only the last one is padded).
+    std::vector<int2> coop;
+    if (L.schedule == 3) {
+        const int nw = L.wg_waves;
+        const int64_t per = std::max(64, L.split / nw);
+        for (size_t i = 0; i < items.size(); i++) {
+            const int64_t n = items[i].end - items[i].begin;
+            int nsub = 1;
+            while (nsub < nw && (int64_t)nsub * per < n) nsub *= 2;
+            if (coop.size() % nw + nsub > (size_t)nw) coop.resize((coop.size() / nw + 1) * nw, make_int2(-1, 0));
+            for (int k = 0; k < nsub; k++) coop.push_back(make_int2((int)i, k | nsub << 8));
+        }
+        if (coop.size() % nw) coop.resize((coop.size() / nw + 1) * nw, make_int2(-1, 0));
+    }
     // CSR of work items per tile (for the deterministic merge flush)
     std::vector<int32_t> tw(ntiles + 1, 0), ids(items.size());
     for (const WorkItem &w : items) tw[w.tile + 1]++;
@@ -578,6 +595,15 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     if (!items.empty())
         MWG_HIP(hipMemcpyAsync(I.work, items.data(), sizeof(WorkItem) * items.size(),
                                hipMemcpyHostToDevice, s));
+    I.coop_wgs = L.schedule == 3 ? (int)(coop.size() / L.wg_waves) : 0;
+    if (!coop.empty()) {
+        if (I.cap_coop < coop.size()) {
+            I.cap_coop = coop.size();
+            MWG_TRY(I.arena.alloc(&p, sizeof(int2) * I.cap_coop));
+            I.coop = (int2 *)p;
+        }
+        MWG_HIP(hipMemcpyAsync(I.coop, coop.data(), sizeof(int2) * coop.size(), hipMemcpyHostToDevice, s));
+    }
     MWG_HIP(hipMemcpyAsync(I.tile_work, tw.data(), 4 * (ntiles + 1), hipMemcpyHostToDevice, s));
     if (!ids.empty())
         MWG_HIP(hipMemcpyAsync(I.work_ids, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, s));
@@ -655,6 +681,11 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
     }
     if (L.schedule == 2 && L.variant != 4)
         return make_error(MW_ERR_UNSUPPORTED, "schedule 2 is implemented for variant 4 only");
+    if (L.schedule == 3 && (L.variant != 4 || L.flush != 2))
+        return make_error(MW_ERR_UNSUPPORTED, "schedule 3 is implemented for variant 4 with flush 2 only");
+    if (L.schedule < 1 || L.schedule > 3) return make_error(MW_ERR_INVALID_ARG, "schedule %d", L.schedule);
+    if (L.wg_waves < 4 && (I.stacks || L.variant != 4))
+        return make_error(MW_ERR_UNSUPPORTED, "workgroups of %d waves are implemented for variant 4 only", L.wg_waves);
     if (I.stacks) {
         L.variant = 5;
         const size_t lds = stack_lds(I.npol, L.tile, L.wg_waves);
@@ -676,7 +707,7 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         };
         // private wave tiles of a large tile size may not fit: without an explicit variant,
         // fall back to the shared-tile kernel of the same lane layout
-        if (L.variant == 4 && !(t && t->variant) && L.schedule != 2 && lds_of(L) > 160 * 1024) L.variant = 2;
+        if (L.variant == 4 && !(t && t->variant) && L.schedule == 1 && lds_of(L) > 160 * 1024) L.variant = 2;
         const size_t lds = lds_of(L);
         if (lds > 160 * 1024)
             return make_error(MW_ERR_UNSUPPORTED, "launch needs %zu B of LDS (tile %d, npol %d)", lds,

@@ -99,6 +99,11 @@ TUNINGS = [
     dict(variant=4, tile=8, wg_waves=16, flush=2),
     dict(variant=4, tile=16, wg_waves=8, flush=1),
     dict(variant=4, tile=8, wg_waves=4, flush=1, split=256, order=2),
+    dict(variant=4, tile=8, wg_waves=1, flush=2, split=300),
+    dict(variant=4, tile=16, wg_waves=2, flush=2),
+    dict(variant=4, tile=8, flush=2, schedule=3, split=512),
+    dict(variant=4, tile=8, flush=2, schedule=3, wg_waves=4, split=2048),
+    dict(variant=4, tile=16, flush=2, schedule=3, wg_waves=4, split=256, order=2),
 ]
 
 
