@@ -94,7 +94,7 @@ typedef struct {
 typedef struct {
     int32_t tile;       /* uv tile edge in cells: 8, 16, 32 or 64 (8 needs W <= 15) */
     int32_t split;      /* max groups per work item (heavy tiles are split), >= 64 */
-    int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 */
+    int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 (1 and 2 with variant 4) */
     int32_t order;      /* 1 = groups sorted by cell (then row sub-position) within a tile,
                            2 = input order */
     int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes, 3 = scatter,
@@ -109,7 +109,10 @@ typedef struct {
                            read from and appended to it, keyed by grid size, W, O, npol
                            and the order of magnitude of the visibility count */
     int32_t schedule;   /* work-item order: 1 = largest first, 2 = Z-order of tiles split into
-                           8 equal-work chunks, one per XCD (variant 4 only) */
+                           8 equal-work chunks, one per XCD (variant 4 only), 3 = largest
+                           first, each item shared by up to wg_waves waves of one workgroup
+                           (about split / wg_waves groups per wave), their tiles summed in
+                           wave order (variant 4 with flush 2 only) */
 } mw_tuning;
 
 typedef struct {
