@@ -191,45 +191,55 @@ __global__ __launch_bounds__(512) void k_fft_rows(const float2 *in, float2 *out,
 }
 
 // Pass 2: columns, in place. N = ny, T = N / 16 threads per column, C columns per
-// workgroup. Loads and stores go column-fastest (C consecutive complex per row); the
+// workgroup. Loads and stores go column-fastest, two columns (16 bytes) per lane; the
 // transforms run with the threads of a wave on one column. The column stride in LDS is
 // 2 mod 16 slots, so the column-fastest accesses hit different banks. Workgroups b, b + 8, ...
 // (the same XCD when workgroups are dealt to the 8 XCDs in turn) take the neighbouring strips
-// that share cache lines.
+// that share cache lines. The output must be 16-byte aligned.
 template <int N, int T, int C>
 __global__ __launch_bounds__(1024) void k_fft_cols(float2 *data, int nx, const float2 *tw, float s,
                                                    ScaleArgs sc) {
     extern __shared__ __align__(16) float2 lds[];
     constexpr int S = lds_len<N>() + 2;
+    constexpr int H = C / 2;         // lanes per row
+    constexpr int RP = (T * C) / H;  // rows per round
     const int nstrip = nx / C;
     // the L = 16 / C strips of one 128-byte line go to workgroups b, b + 8, ... (one XCD)
     constexpr int L = C >= 16 ? 1 : 16 / C;
     int b = blockIdx.x;
     if ((int)(gridDim.x / (8 * L)) * 8 * L > b) b = (b / (8 * L)) * 8 * L + (b % 8) * L + (b / 8) % L;
     const int p = b / nstrip, x0 = (b % nstrip) * C;
-    float2 *base = data + (int64_t)p * N * nx + x0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, h = tid % H, r0 = tid / H;
     FftTwiddles<N, T> tws;
     tws.load(tid % T, tw);
-    // global -> LDS, column-fastest
+    // global -> LDS
     {
-        const int c = tid % C, r0 = tid / C;
+        const float4 *src = (const float4 *)(data + (int64_t)p * N * nx + x0) + h;
 #pragma unroll
-        for (int y = r0; y < N; y += T) lds[c * S + lpad(y)] = base[(int64_t)y * nx + c];
+        for (int y = r0; y < N; y += RP) {
+            const float4 v = src[(int64_t)y * (nx / 2)];
+            lds[(2 * h) * S + lpad(y)] = make_float2(v.x, v.y);
+            lds[(2 * h + 1) * S + lpad(y)] = make_float2(v.z, v.w);
+        }
     }
     __syncthreads();
     tws.run(lds + (tid / T) * S, tid % T, s);
     // LDS -> global with the output sign, the constant and the correction
     {
-        const int c = tid % C, r0 = tid / C;
-        const int x = x0 + c;
-        const float cx = sc.divide_out ? sc.corrx[x] : 1.0f;
+        float4 *dst = (float4 *)(data + (int64_t)p * N * nx + x0) + h;
+        const int x = x0 + 2 * h;
+        const float cx0 = sc.divide_out ? sc.corrx[x] : 1.0f, cx1 = sc.divide_out ? sc.corrx[x + 1] : 1.0f;
 #pragma unroll
-        for (int y = r0; y < N; y += T) {
-            float f = ((x + y) & 1) ? -sc.gsign : sc.gsign;
-            if (sc.divide_out) f = f / (cx * sc.corry[y]);
-            const float2 v = lds[c * S + lpad(y)];
-            base[(int64_t)y * nx + c] = make_float2(f * v.x, f * v.y);
+        for (int y = r0; y < N; y += RP) {
+            float f0 = ((x + y) & 1) ? -sc.gsign : sc.gsign;
+            float f1 = -f0;
+            if (sc.divide_out) {
+                const float cy = sc.corry[y];
+                f0 = f0 / (cx0 * cy);
+                f1 = f1 / (cx1 * cy);
+            }
+            const float2 v0 = lds[(2 * h) * S + lpad(y)], v1 = lds[(2 * h + 1) * S + lpad(y)];
+            dst[(int64_t)y * (nx / 2)] = make_float4(f0 * v0.x, f0 * v0.y, f1 * v1.x, f1 * v1.y);
         }
     }
 }
@@ -252,7 +262,8 @@ Status launch_cols(float2 *data, int nx, int npol, const float2 *tw, float s, co
                    hipStream_t st) {
     constexpr int T = N / 16;
     // columns per workgroup: about 70 KB of LDS, so that two workgroups share a CU
-    constexpr int C = (8192 / N) < 1 ? 1 : ((8192 / N) > 16 ? 16 : 8192 / N);
+    constexpr int C = (8192 / N) > 16 ? 16 : 8192 / N;
+    static_assert(C >= 2 && (C & 1) == 0, "two columns per lane");
     if (nx % C != 0) return make_error(MW_ERR_UNSUPPORTED, "nx %d not a multiple of %d", nx, C);
     const size_t lds = sizeof(float2) * (size_t)C * (lds_len<N>() + 2);
     hipLaunchKernelGGL((k_fft_cols<N, T, C>), dim3((nx / C) * npol), dim3(T * C), lds, st, data, nx, tw, s, sc);

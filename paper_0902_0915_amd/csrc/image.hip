@@ -105,7 +105,9 @@ void image_release(Instance &I) {
 
 Status launch_image(Instance &I, const float2 *in, float2 *out, int direction, int correct,
                     hipStream_t s) {
-    if (fft2d_supported(I.nx, I.ny)) {
+    // the two-pass transform's column pass moves 16 bytes per lane: it needs a 16-byte aligned
+    // output (a view at an odd complex offset goes through rocFFT instead)
+    if (fft2d_supported(I.nx, I.ny) && ((uintptr_t)out & 15) == 0) {
         if (!I.twx) {
             MWG_TRY(fft2d_twiddles(I.arena, I.nx, &I.twx, s));
             MWG_TRY(fft2d_twiddles(I.arena, I.ny, &I.twy, s));
