@@ -68,7 +68,7 @@ struct Launch {
     int tile = 32;     // T (power of two)
     int split = 8192;  // max groups per work item
     int wg_waves = 8;  // waves per workgroup
-    int order = 1;     // 1 cell-sorted, 2 input order within tile
+    int order = 1;     // 1 cell-sorted, 2 input order within tile, 3 cell-sorted along the radius
     int variant = 1;   // gridder variant
     int flush = 1;     // 1 atomic, 2 deterministic merge
     int schedule = 1;  // 1 largest first, 2 Z-order chunks per XCD, 3 workgroup-cooperative items

@@ -135,7 +135,7 @@ __global__ void k_positions(PosArgs a) {
 
 // Sort keys: tile-major, then cell within the tile (order 1) or nothing (order 2: the stable
 // sort keeps input order). Dropped groups get the all-ones key of the sorted width.
-__global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int order,
+__global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int nx, int ny, int order,
                        uint32_t sentinel, uint32_t *keys) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -145,9 +145,25 @@ __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int orde
         const uint32_t cx = p & 0xFFFu, cy = (p >> 12) & 0xFFFu;
         const uint32_t tile = (cy >> tb) * (uint32_t)ntx + (cx >> tb);
         const uint32_t mask = (1u << tb) - 1u;
-        // order 1: (tile, cell row, cell column, row sub-position)
-        k = order == 1 ? (tile << (2 * tb + 4)) | ((cy & mask) << (tb + 4)) | ((cx & mask) << 4) | (p >> 28)
-                       : tile;
+        if (order == 2) {
+            k = tile;
+        } else {
+            // order 1: (tile, cell row, cell column, row sub-position). Order 3 takes the cells
+            // column by column instead in tiles that lie farther from the grid centre in v than
+            // in u: the channels of one baseline fall on radially neighbouring cells, which
+            // are then consecutive in either kind of tile.
+            uint32_t a = cy & mask, b = cx & mask;
+            if (order == 3) {
+                const int half = 1 << (tb - 1);
+                const int du = abs((int)((cx >> tb) << tb) + half - nx / 2);
+                const int dv = abs((int)((cy >> tb) << tb) + half - ny / 2);
+                if (dv > du) {
+                    a = cx & mask;
+                    b = cy & mask;
+                }
+            }
+            k = (tile << (2 * tb + 4)) | (a << (tb + 4)) | (b << 4) | (p >> 28);
+        }
     }
     keys[g] = k;
 }
@@ -422,7 +438,7 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     if ((1 << tb) != L.tile) return make_error(MW_ERR_INVALID_ARG, "tile %d is not a power of two", L.tile);
     const int ntx = (I.nx + L.tile - 1) / L.tile, nty = (I.ny + L.tile - 1) / L.tile;
     const int64_t ntiles = (int64_t)ntx * nty;
-    const int cellbits = L.order == 1 ? 2 * tb + 4 : 0; // key bits below the tile index
+    const int cellbits = L.order != 2 ? 2 * tb + 4 : 0; // key bits below the tile index
     const uint64_t maxkey = (uint64_t)ntiles << cellbits; // exclusive bound of valid keys
     const int keybits = bitlength(maxkey);
     if (keybits > 31) return make_error(MW_ERR_UNSUPPORTED, "sort key wider than 31 bits");
@@ -438,7 +454,7 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         MWG_TRY(vals2.alloc(4 * ng));
         uint32_t *skeys = nullptr, *sperm = nullptr;
         if (ng > 0) {
-            hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, L.order,
+            hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, I.nx, I.ny, L.order,
                                sentinel, keys.as<uint32_t>());
             MWG_HIP(hipGetLastError());
             MWG_TRY(radix_sort(keys.as<uint32_t>(), keys2.as<uint32_t>(), vals.as<uint32_t>(),
@@ -643,7 +659,7 @@ static Launch default_launch(const Instance &I) {
     // with a short tail), between 256 and 8192 groups.
     L.split = 256;
     while (L.split < 8192 && (int64_t)L.split * 4096 < I.nkept) L.split *= 2;
-    L.order = 1;
+    L.order = 3;
     if (I.stacks) {
         // gather by output tile, one private tile per wavefront
         L.tile = I.npol >= 2 ? 16 : 32;
@@ -655,7 +671,7 @@ static Launch default_launch(const Instance &I) {
         // private 8x8 tiles per wavefront, merge pass: no LDS float atomics, no global atomics
         L.tile = 8;
         L.variant = 4;
-        L.wg_waves = 8;
+        L.wg_waves = 4;
         L.flush = 2;
     } else {
         L.tile = I.npol >= 2 ? 32 : 64;

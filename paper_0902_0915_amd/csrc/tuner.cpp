@@ -133,7 +133,7 @@ Status autotune(Instance &I, hipStream_t s) {
                         t.split = split;
                         t.schedule = sched;
                         t.flush = flush;
-                        t.order = 1;
+                        t.order = 3;
                         t.variant = v4 ? 4 : (I.W * I.W <= 64 ? 1 : 3);
                         if (!v4 && sched == 2) continue;
                         if (v4 && tile == 32) continue;          // private 32x32 tiles: too few waves

@@ -112,7 +112,7 @@ def test_plan_rejects_ant_mismatch_and_bad_tuning(mw):
     h = ctypes.c_void_p()
     assert mw.lib().mw_grid_plan(ctypes.byref(h), (mw.MwInstance * 1)(d), 1, None, None) == 1
     d, keep = _instance(mw)
-    for bad in (dict(tile=48), dict(split=10), dict(wg_waves=3), dict(order=3), dict(variant=9),
+    for bad in (dict(tile=48), dict(split=10), dict(wg_waves=3), dict(order=4), dict(variant=9),
                 dict(flush=5), dict(schedule=4)):
         t = mw.MwTuning(**bad)
         st = mw.lib().mw_grid_plan(ctypes.byref(h), (mw.MwInstance * 1)(d), 1, ctypes.byref(t), None)

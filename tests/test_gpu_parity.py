@@ -104,6 +104,8 @@ TUNINGS = [
     dict(variant=4, tile=8, flush=2, schedule=3, split=512),
     dict(variant=4, tile=8, flush=2, schedule=3, wg_waves=4, split=2048),
     dict(variant=4, tile=16, flush=2, schedule=3, wg_waves=4, split=256, order=2),
+    dict(variant=4, tile=8, flush=2, order=3, split=300),
+    dict(variant=2, tile=16, order=3),
 ]
 
 
