@@ -135,6 +135,39 @@ __global__ void k_positions(PosArgs a) {
 
 // Sort keys: tile-major, then cell within the tile (order 1) or nothing (order 2: the stable
 // sort keeps input order). Dropped groups get the all-ones key of the sorted width.
+// Rank of cell (cx, cy) among the cells of its tile ordered by their line across the radius
+// (the direction from the grid centre to the tile centre), then by their position along it,
+// then by cell index. Integer arithmetic on cell-centre offsets doubled and a direction scaled
+// to 2^10, so that every comparison is exact and the ranks are a permutation of the tile's
+// cells. Tiles above 16 x 16 keep rows in tiles that lie more in u than in v, and columns
+// otherwise.
+__device__ inline uint32_t radial_rank(uint32_t cx, uint32_t cy, int tb, int nx, int ny) {
+    const int T = 1 << tb, mask = T - 1;
+    const int lx = (int)(cx & (uint32_t)mask), ly = (int)(cy & (uint32_t)mask);
+    const int du = (int)((cx >> tb) << tb) + T / 2 - nx / 2;
+    const int dv = (int)((cy >> tb) << tb) + T / 2 - ny / 2;
+    if (tb > 4)
+        return abs(dv) > abs(du) ? (uint32_t)((lx << tb) | ly) : (uint32_t)((ly << tb) | lx);
+    const float len = sqrtf((float)du * (float)du + (float)dv * (float)dv);
+    const int ex = len > 0.0f ? (int)lrintf(1024.0f * (float)du / len) : 1024;
+    const int ey = len > 0.0f ? (int)lrintf(1024.0f * (float)dv / len) : 0;
+    // line index: the cross-radial coordinate in cells, rounded (units of 1/2048 cell);
+    // position: the radial coordinate (same units)
+    auto line = [&](int x, int y) {
+        const int v = -ey * (2 * x - (T - 1)) + ex * (2 * y - (T - 1));
+        return (v + 1024 + (64 << 11)) >> 11;  // floor((v + 1024) / 2048) + 64, non-negative
+    };
+    auto along = [&](int x, int y) { return ex * (2 * x - (T - 1)) + ey * (2 * y - (T - 1)); };
+    const int l0 = line(lx, ly), a0 = along(lx, ly), i0 = ly * T + lx;
+    uint32_t rank = 0;
+    for (int y = 0; y < T; y++)
+        for (int x = 0; x < T; x++) {
+            const int l = line(x, y), a = along(x, y), i = y * T + x;
+            rank += (l < l0 || (l == l0 && (a < a0 || (a == a0 && i < i0)))) ? 1u : 0u;
+        }
+    return rank;
+}
+
 __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int nx, int ny, int order,
                        uint32_t sentinel, uint32_t *keys) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -148,21 +181,13 @@ __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int nx, 
         if (order == 2) {
             k = tile;
         } else {
-            // order 1: (tile, cell row, cell column, row sub-position). Order 3 takes the cells
-            // column by column instead in tiles that lie farther from the grid centre in v than
-            // in u: the channels of one baseline fall on radially neighbouring cells, which
-            // are then consecutive in either kind of tile.
-            uint32_t a = cy & mask, b = cx & mask;
-            if (order == 3) {
-                const int half = 1 << (tb - 1);
-                const int du = abs((int)((cx >> tb) << tb) + half - nx / 2);
-                const int dv = abs((int)((cy >> tb) << tb) + half - ny / 2);
-                if (dv > du) {
-                    a = cx & mask;
-                    b = cy & mask;
-                }
-            }
-            k = (tile << (2 * tb + 4)) | (a << (tb + 4)) | (b << 4) | (p >> 28);
+            // order 1: (tile, cell row, cell column, row sub-position). Order 3 replaces the
+            // cell's (row, column) by its rank along the tile's radial direction: the channels
+            // of one baseline fall on radially neighbouring cells, which this makes
+            // consecutive.
+            uint32_t cell = ((cy & mask) << tb) | (cx & mask);
+            if (order == 3) cell = radial_rank(cx, cy, tb, nx, ny);
+            k = (tile << (2 * tb + 4)) | (cell << 4) | (p >> 28);
         }
     }
     keys[g] = k;
