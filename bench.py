@@ -43,8 +43,8 @@ KERNEL_NAMES = {1: "k_grid_taplanes", 2: "k_grid_collanes", 3: "k_grid_scatter",
 GRIDDER_SOURCES = ("paper_0902_0915_amd/csrc/gridder_core.h", "paper_0902_0915_amd/csrc/grid.hip",
                    "paper_0902_0915_amd/csrc/plan.hip", "paper_0902_0915_amd/csrc/internal.h")
 MEASURED_TRAFFIC = {
-    "sha256": "cc1ad18224ca7c49d7089ac581acc4ca8182fb3f5490cf5233361541213dfbf3",
-    "fetch_kib": 1.8813e6, "write_kib": 1.7478e5, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sha256": "4d839b1bfc231c9b48cdc245771d8dfe10e41155b48ebbc126eb5dad0c6b954f",
+    "fetch_kib": 1.7999e6, "write_kib": 1.7467e5, "fetch_scale": 2.0, "write_scale": 1.0,
     "profile": "profiles/k_grid_wavetiles_mwa2048.md",
 }
 

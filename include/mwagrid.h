@@ -96,7 +96,9 @@ typedef struct {
     int32_t split;      /* max groups per work item (heavy tiles are split), >= 64 */
     int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 (1 and 2 with variant 4) */
     int32_t order;      /* 1 = groups sorted by cell (then row sub-position) within a tile,
-                           2 = input order */
+                           cells row by row, 2 = input order, 3 (default) = as 1 with the
+                           cells ranked line by line across the direction from the grid
+                           centre to the tile (rows or columns for tiles above 16) */
     int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes, 3 = scatter,
                            4 = column lanes with a private tile per wavefront,
                            5 = kernel stacks, gathered by output tile (chosen for stacks) */
