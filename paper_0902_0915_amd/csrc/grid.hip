@@ -141,11 +141,14 @@ __device__ inline void flush_tile(const GridArgs &a, const float *tile, int flus
             }
         }
     } else {
+        // cell-major slice: the 2 * NPOL components of a cell contiguous
         float *out = a.partial + (int64_t)blockIdx.x * (2 * NPOL) * R * R;
         for (int idx = threadIdx.x; idx < R * R; idx += nthreads) {
             const int r = idx / R, c = idx - r * R;
+            float v[2 * NPOL];
 #pragma unroll
-            for (int q = 0; q < 2 * NPOL; q++) out[(int64_t)q * R * R + idx] = tile[q * PL + r * STR + c];
+            for (int q = 0; q < 2 * NPOL; q++) v[q] = tile[q * PL + r * STR + c];
+            store_cell<2 * NPOL>(out + (int64_t)idx * 2 * NPOL, v);
         }
     }
 }
@@ -488,8 +491,8 @@ __global__ __launch_bounds__(1024) void k_grid_wavetiles_coop(GridArgs a) {
         const int nsub = __builtin_amdgcn_readfirstlane(tj.y >> 8);
         const float *t0 = smem + ntab + j * per_wave + kStageFloats;
         float *out = a.partial + (int64_t)it * NC * RR;
-        for (int idx = tid; idx < NC * RR; idx += nthreads) {
-            const int q = idx / RR, rr = idx - q * RR;
+        for (int idx = tid; idx < NC * RR; idx += nthreads) {  // cell-major, as the merge reads it
+            const int rr = idx / NC, q = idx - rr * NC;
             const int r = rr / R, col = rr - r * R;
             const int off = q * a.plane + r * a.str + col;
             float v = t0[off];

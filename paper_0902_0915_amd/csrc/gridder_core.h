@@ -63,6 +63,35 @@ __device__ inline void wave_tile_add(float *p, int STR, int sg, const float (&ac
         if (sg + NSG * k < W) p[NSG * k * STR] = old[k] + acc[k];
 }
 
+// The NC = 2 * npol components of one cell of a partial tile (cell-major layout, 8 * NC-byte
+// aligned) as one or two vector accesses.
+template <int NC>
+__device__ inline void store_cell(float *dst, const float (&v)[NC]) {
+    if constexpr (NC == 2) {
+        *(float2 *)dst = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NC; q += 4) *(float4 *)(dst + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+    }
+}
+template <int NC>
+__device__ inline void add_cell(const float *src, float (&acc)[NC]) {
+    if constexpr (NC == 2) {
+        const float2 a = *(const float2 *)src;
+        acc[0] += a.x;
+        acc[1] += a.y;
+    } else {
+#pragma unroll
+        for (int q = 0; q < NC; q += 4) {
+            const float4 a = *(const float4 *)(src + q);
+            acc[q] += a.x;
+            acc[q + 1] += a.y;
+            acc[q + 2] += a.z;
+            acc[q + 3] += a.w;
+        }
+    }
+}
+
 // Per-wave staging area of the wave-tile gridder: 32 groups at a time, each as its 2 * npol
 // visibility components (slots 0..7) and its column-tap row T[px][0..7] (slots 8..15), at a
 // stride of 20 floats: the 16-byte stores of 8 consecutive groups then cover all 32 banks
@@ -239,11 +268,15 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
             }
         }
     } else if (c.flush == 2) {
+        // the item's slice of the partial buffer: cell-major, the NC components of a cell
+        // contiguous
         float *out = c.partial;
         for (int idx = lane; idx < R * R; idx += 64) {
             const int r = idx / R, col = idx - r * R;
+            float v[NC];
 #pragma unroll
-            for (int q = 0; q < NC; q++) out[(int64_t)q * R * R + idx] = tile[q * PL + r * STR + col];
+            for (int q = 0; q < NC; q++) v[q] = tile[q * PL + r * STR + col];
+            store_cell<NC>(out + (int64_t)idx * NC, v);
         }
     }
 }
@@ -300,11 +333,8 @@ __device__ inline void merge_cell(float2 *grid, const float *partial, const int3
             const int c = x - (ttx * T - h);
             if (c < 0 || c >= R) continue;
             const int2 rg = rng[(tty - m.ty_lo) * m.ntxb + (ttx - m.tx_lo)];
-            for (int k = rg.x; k < rg.y; k++) {
-                const float *src = partial + (int64_t)work_ids[k] * NC * R * R + r * R + c;
-#pragma unroll
-                for (int q = 0; q < NC; q++) acc[q] += src[(int64_t)q * R * R];
-            }
+            for (int k = rg.x; k < rg.y; k++)
+                add_cell<NC>(partial + ((int64_t)work_ids[k] * R * R + r * R + c) * NC, acc);
         }
     }
 #pragma unroll

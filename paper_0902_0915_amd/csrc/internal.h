@@ -123,7 +123,7 @@ struct Instance {
     int32_t *mblocks = nullptr;   // merge blocks (by * bpr + bx): those some work item reaches,
     int n_mblocks = 0;            //   then the n_zblocks that none reaches (written as zeros)
     int n_zblocks = 0;
-    float *partial = nullptr;     // merge flush scratch: [nwork][2*npol][R*R]
+    float *partial = nullptr;     // merge flush scratch: [nwork][R*R][2*npol] (cell-major)
     size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)
     float *tab = nullptr;         // [O][W] + 8 floats of padding
