@@ -541,19 +541,27 @@ __global__ __launch_bounds__(1024) void k_grid_scatter(GridArgs a, int flush) {
 
 // Merge pass of flush 2: every grid cell sums the partial tiles of all work items whose
 // (haloed) tile covers it, in a fixed order.
-// The merge pass over the listed blocks that some work item reaches, one per workgroup.
-// Workgroups are dealt to the 8 XCDs in turn; workgroup w takes list entry
-// (w mod 8) * chunk + w / 8, so each XCD merges one contiguous band of the list and the
-// blocks that read the same partial tiles share that XCD's L2.
+// One launch covers the listed blocks that some work item reaches (merged), then the nzero
+// listed blocks that none reaches (zeroed), one block per workgroup. The first 8 * chunk
+// workgroups merge, chunk = ceil(nblocks / 8): they are dealt to the 8 XCDs in turn and
+// workgroup w takes list entry (w mod 8) * chunk + w / 8, so each XCD merges one contiguous
+// band of the list and the blocks that read the same partial tiles share that XCD's L2.
 template <int NPOL>
 __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const float *partial,
                                                               const int32_t *tile_work, const int32_t *work_ids,
-                                                              const int32_t *blocks, int nblocks, int nx, int ny,
-                                                              int lgT, int ntx, int nty, int W, int accumulate) {
+                                                              const int32_t *blocks, int nblocks, int nzero, int nx,
+                                                              int ny, int lgT, int ntx, int nty, int W, int accumulate) {
     __shared__ int2 rng[kMergeTiles];
     const int bpr = (nx + kMergeB - 1) / kMergeB, h = (W - 1) / 2;
     const int tid = threadIdx.x;
-    const int chunk = (int)(gridDim.x >> 3);
+    const int chunk = (nblocks + 7) / 8;
+    if ((int)blockIdx.x >= 8 * chunk) {
+        const int z = (int)blockIdx.x - 8 * chunk;
+        if (z >= nzero) return;
+        const int b = blocks[nblocks + z], by = b / bpr, bx = b - by * bpr;
+        zero_block<NPOL>(grid, nx, ny, bx * kMergeB, by * kMergeB);
+        return;
+    }
     const int e = (int)(blockIdx.x & 7u) * chunk + (int)(blockIdx.x >> 3);
     if (e >= nblocks) return;
     const int b = blocks[e], by = b / bpr, bx = b - by * bpr;
@@ -563,15 +571,6 @@ __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const
     __syncthreads();
     merge_cell<NPOL>(grid, partial, work_ids, nx, ny, lgT, W, accumulate, m, rng, x0 + (tid & (kMergeB - 1)),
                      y0 + tid / kMergeB);
-}
-
-// Zeros of the listed blocks that no work item reaches, one per workgroup.
-template <int NPOL>
-__global__ __launch_bounds__(kMergeB * kMergeB) void k_zero_blocks(float2 *grid, const int32_t *blocks, int nx,
-                                                                    int ny) {
-    const int bpr = (nx + kMergeB - 1) / kMergeB;
-    const int b = blocks[blockIdx.x], by = b / bpr, bx = b - by * bpr;
-    zero_block<NPOL>(grid, nx, ny, bx * kMergeB, by * kMergeB);
 }
 
 template <int NPOL>
@@ -634,17 +633,13 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
     }
     if (I.timing) MWG_HIP(hipEventRecord(I.tev[1], s));
     if (flush == 2) {
-        if (I.n_mblocks > 0) {
+        const int nzero = accumulate ? 0 : I.n_zblocks;
+        if (I.n_mblocks + nzero > 0) {
             const int chunk = (I.n_mblocks + 7) / 8;
-            hipLaunchKernelGGL(k_merge<NPOL>, dim3(8 * chunk), dim3(kMergeB * kMergeB), 0, s, a.grid,
+            hipLaunchKernelGGL(k_merge<NPOL>, dim3(8 * chunk + nzero), dim3(kMergeB * kMergeB), 0, s, a.grid,
                                (const float *)I.partial, (const int32_t *)I.tile_work, (const int32_t *)I.work_ids,
-                               (const int32_t *)I.mblocks, I.n_mblocks, I.nx, I.ny, ilog2(L.tile), I.ntx, I.nty,
-                               I.W, accumulate);
-            MWG_HIP(hipGetLastError());
-        }
-        if (I.n_zblocks > 0 && !accumulate) {
-            hipLaunchKernelGGL(k_zero_blocks<NPOL>, dim3(I.n_zblocks), dim3(kMergeB * kMergeB), 0, s, a.grid,
-                               (const int32_t *)I.mblocks + I.n_mblocks, I.nx, I.ny);
+                               (const int32_t *)I.mblocks, I.n_mblocks, nzero, I.nx, I.ny, ilog2(L.tile), I.ntx,
+                               I.nty, I.W, accumulate);
             MWG_HIP(hipGetLastError());
         }
     }
