@@ -106,6 +106,8 @@ TUNINGS = [
     dict(variant=4, tile=16, flush=2, schedule=3, wg_waves=4, split=256, order=2),
     dict(variant=4, tile=8, flush=2, order=3, split=300),
     dict(variant=2, tile=16, order=3),
+    dict(variant=1, tile=32, order=3, flush=2),
+    dict(variant=3, tile=64, order=3),
 ]
 
 
