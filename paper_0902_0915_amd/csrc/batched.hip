@@ -151,6 +151,7 @@ template <int NPOL>
 __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge_batched(const BatchDesc *desc, const int2 *pairs,
                                                                      int lgT, int W) {
     __shared__ int2 rng[kMergeTiles];
+    __shared__ int fid[kMergeTiles];
     const int h = (W - 1) / 2, tid = threadIdx.x;
     const int2 pr = pairs[blockIdx.x];
     const BatchDesc &d = desc[pr.x];
@@ -158,9 +159,9 @@ __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge_batched(const Batch
     const int by = pr.y / bpr, bx = pr.y - by * bpr;
     const int x0 = bx * kMergeB, y0 = by * kMergeB;
     const MergeBounds m = merge_bounds(x0, y0, h, lgT, d.ntx, d.nty);
-    if (tid < 32) merge_stage(d.tile_work, d.ntx, m, tid, rng);
+    if (tid < 32) merge_stage(d.tile_work, d.work_ids, d.ntx, m, tid, rng, fid);
     __syncthreads();
-    merge_cell<NPOL>(d.grid, d.partial, d.work_ids, d.nx, d.ny, lgT, W, d.accumulate, m, rng,
+    merge_cell<NPOL>(d.grid, d.partial, d.work_ids, d.nx, d.ny, lgT, W, d.accumulate, m, rng, fid,
                      x0 + (tid & (kMergeB - 1)), y0 + tid / kMergeB);
 }
 

@@ -552,6 +552,7 @@ __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const
                                                               const int32_t *blocks, int nblocks, int nzero, int nx,
                                                               int ny, int lgT, int ntx, int nty, int W, int accumulate) {
     __shared__ int2 rng[kMergeTiles];
+    __shared__ int fid[kMergeTiles];
     const int bpr = (nx + kMergeB - 1) / kMergeB, h = (W - 1) / 2;
     const int tid = threadIdx.x;
     const int chunk = (nblocks + 7) / 8;
@@ -567,9 +568,9 @@ __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const
     const int b = blocks[e], by = b / bpr, bx = b - by * bpr;
     const int x0 = bx * kMergeB, y0 = by * kMergeB;
     const MergeBounds m = merge_bounds(x0, y0, h, lgT, ntx, nty);
-    if (tid < 32) merge_stage(tile_work, ntx, m, tid, rng);
+    if (tid < 32) merge_stage(tile_work, work_ids, ntx, m, tid, rng, fid);
     __syncthreads();
-    merge_cell<NPOL>(grid, partial, work_ids, nx, ny, lgT, W, accumulate, m, rng, x0 + (tid & (kMergeB - 1)),
+    merge_cell<NPOL>(grid, partial, work_ids, nx, ny, lgT, W, accumulate, m, rng, fid, x0 + (tid & (kMergeB - 1)),
                      y0 + tid / kMergeB);
 }
 

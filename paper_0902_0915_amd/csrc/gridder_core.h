@@ -304,37 +304,74 @@ __device__ inline MergeBounds merge_bounds(int x0, int y0, int h, int lgT, int n
 }
 
 // Entry e of block (x0, y0)'s tile-range table.
-__device__ inline void merge_stage(const int32_t *tile_work, int ntx, const MergeBounds &m, int e, int2 *rng) {
+// (fid: the tile's first work item, or -1 for a tile with none)
+__device__ inline void merge_stage(const int32_t *tile_work, const int32_t *work_ids, int ntx, const MergeBounds &m,
+                                   int e, int2 *rng, int *fid) {
     if (e < m.ntxb * m.ntyb) {
         const int t = (m.ty_lo + e / m.ntxb) * ntx + m.tx_lo + e % m.ntxb;
-        rng[e] = make_int2(tile_work[t], tile_work[t + 1]);
+        const int2 rg = make_int2(tile_work[t], tile_work[t + 1]);
+        rng[e] = rg;
+        fid[e] = rg.y > rg.x ? work_ids[rg.x] : -1;
     }
 }
 
 template <int NPOL>
 __device__ inline void merge_cell(float2 *grid, const float *partial, const int32_t *work_ids, int nx, int ny,
                                   int lgT, int W, int accumulate, const MergeBounds &m, const int2 *rng,
-                                  int x, int y) {
+                                  const int *fid, int x, int y) {
     constexpr int NC = 2 * NPOL;
     const int T = 1 << lgT, h = (W - 1) / 2, R = T + W - 1;
     if (x >= nx || y >= ny) return;
+    const int txc = x >> lgT, tyc = y >> lgT;
     float acc[NC];
 #pragma unroll
     for (int q = 0; q < NC; q++) acc[q] = 0.0f;
-    const int txc = x >> lgT, tyc = y >> lgT;
-    for (int dy = -1; dy <= 1; dy++) {
-        const int tty = tyc + dy;
-        if (tty < m.ty_lo || tty >= m.ty_lo + m.ntyb) continue;
-        const int r = y - (tty * T - h);
-        if (r < 0 || r >= R) continue;
-        for (int dx = -1; dx <= 1; dx++) {
-            const int ttx = txc + dx;
-            if (ttx < m.tx_lo || ttx >= m.tx_lo + m.ntxb) continue;
-            const int c = x - (ttx * T - h);
-            if (c < 0 || c >= R) continue;
-            const int2 rg = rng[(tty - m.ty_lo) * m.ntxb + (ttx - m.tx_lo)];
-            for (int k = rg.x; k < rg.y; k++)
-                add_cell<NC>(partial + ((int64_t)work_ids[k] * R * R + r * R + c) * NC, acc);
+    if constexpr (NC <= 4) {
+        // few components: load the first work item's value of each of the <= 3 x 3 covering
+        // tiles with all loads in flight together, then add them, and any further items of a
+        // split tile, in the fixed order (tile row, tile column, then the tile's items)
+        float first[9][NC];
+        int ent[9], off[9];
+#pragma unroll
+        for (int t = 0; t < 9; t++) {
+            const int tty = tyc + t / 3 - 1, ttx = txc + t % 3 - 1;
+            const int r = y - (tty * T - h), c = x - (ttx * T - h);
+            const bool ok = tty >= m.ty_lo && tty < m.ty_lo + m.ntyb && r >= 0 && r < R && ttx >= m.tx_lo &&
+                            ttx < m.tx_lo + m.ntxb && c >= 0 && c < R;
+            ent[t] = ok ? (tty - m.ty_lo) * m.ntxb + (ttx - m.tx_lo) : -1;
+            off[t] = r * R + c;
+            const int f = ok ? fid[ent[t]] : -1;
+#pragma unroll
+            for (int q = 0; q < NC; q++) first[t][q] = 0.0f;
+            if (f >= 0) add_cell<NC>(partial + ((int64_t)f * R * R + off[t]) * NC, first[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; t++) {
+            if (ent[t] < 0) continue;
+            const int2 rg = rng[ent[t]];
+            if (rg.y <= rg.x) continue;
+#pragma unroll
+            for (int q = 0; q < NC; q++) acc[q] += first[t][q];
+            for (int k = rg.x + 1; k < rg.y; k++)
+                add_cell<NC>(partial + ((int64_t)work_ids[k] * R * R + off[t]) * NC, acc);
+        }
+    } else {
+        // 8 components: the same order, one tile at a time (holding nine tiles' values would
+        // cost more registers than the overlap gains)
+        for (int dy = -1; dy <= 1; dy++) {
+            const int tty = tyc + dy;
+            if (tty < m.ty_lo || tty >= m.ty_lo + m.ntyb) continue;
+            const int r = y - (tty * T - h);
+            if (r < 0 || r >= R) continue;
+            for (int dx = -1; dx <= 1; dx++) {
+                const int ttx = txc + dx;
+                if (ttx < m.tx_lo || ttx >= m.tx_lo + m.ntxb) continue;
+                const int c = x - (ttx * T - h);
+                if (c < 0 || c >= R) continue;
+                const int2 rg = rng[(tty - m.ty_lo) * m.ntxb + (ttx - m.tx_lo)];
+                for (int k = rg.x; k < rg.y; k++)
+                    add_cell<NC>(partial + ((int64_t)work_ids[k] * R * R + r * R + c) * NC, acc);
+            }
         }
     }
 #pragma unroll
