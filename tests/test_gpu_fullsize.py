@@ -40,6 +40,7 @@ def test_full_size_launch_is_the_benchmarked_one(full):
     info = full["info"]
     assert info["ngroups"] == 33_488_896 and full["vis"].shape == (33_488_896, 4)
     assert info["variant"] == 4 and info["flush"] == 2 and info["tile"] == 8
+    assert info["order"] == 3 and info["wg_waves"] == 4 and info["schedule"] == 1
     assert info["nkept"] == int(full["keep"].sum())
 
 
