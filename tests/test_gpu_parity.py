@@ -157,15 +157,16 @@ def test_grid_parity_tiny_1pol(mw, tiny, tuning):
     assert nl2(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("tuning", [None, dict(schedule=3, split=512)], ids=str)
 @pytest.mark.parametrize("npol", [1, 2])
-def test_grid_parity_weights_gains_flags(mw, small_mwa, npol):
+def test_grid_parity_weights_gains_flags(mw, small_mwa, npol, tuning):
     rng = np.random.default_rng(npol)
     wl = synth.mwa_scale(seed=2003, nant=48, nchan=6, ntime=2, npol=npol, n=256, nsrc=20)
     wl.flags = (rng.random(wl.ngroups) < 0.15).astype(np.uint8)
     wl.weights = rng.uniform(0.2, 2.0, wl.ngroups).astype(np.float32)
     gains = synth.random_gains(wl.nant, rng)
     ref = oracle_grid(wl, wl.vis, weights=wl.weights.astype(np.float64), gains=gains)
-    with _plan(mw, wl) as plan:
+    with _plan(mw, wl, tuning=tuning) as plan:
         got = to_host(plan.grid(to_dev(wl.vis), gains=to_dev(gains)))
     assert nl2(got, ref) <= TOL
 
