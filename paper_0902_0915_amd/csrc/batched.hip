@@ -50,6 +50,7 @@ struct BatchItem {
 
 struct Batch {
     int ninst = 0, npol = 1, W = 7, O = 8, T = 8, waves = 8, STR = 0, PL = 0, nitems = 0;
+    int dthreads = 256;  // threads per degridder workgroup
     int grid_blocks = 0;     // gridder workgroups (waves of them, one work item per wave)
     int64_t merge_blocks = 0, zero_blocks = 0, prologue_n = 0;
     int ant_in_lds = 0;
@@ -273,7 +274,7 @@ Status enqueue_degrid(Batch &B, int64_t ndrop_total, hipStream_t s) {
         MWG_HIP(hipGetLastError());
     }
     if (B.nitems > 0) {
-        hipLaunchKernelGGL(k_degrid_batched<NPOL>, dim3(B.nitems), dim3(256), B.degrid_lds, s, B.d_desc,
+        hipLaunchKernelGGL(k_degrid_batched<NPOL>, dim3(B.nitems), dim3(B.dthreads), B.degrid_lds, s, B.d_desc,
                            B.d_items, B.T, B.W, B.O, B.ant_in_lds);
         MWG_HIP(hipGetLastError());
     }
@@ -411,6 +412,11 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     // time, which stay in cache. Interleaving all instances largest-first spreads the random
     // gathers over every instance at once and runs ~4x slower.
     B->nitems = (int)items.size();
+    {
+        int64_t kept = 0;
+        for (Instance *I : P.inst) kept += I->nkept;
+        B->dthreads = degrid_threads(kept, B->nitems);
+    }
     B->merge_blocks = mstart[B->ninst];
     B->zero_blocks = zstart[B->ninst];
     void *p;

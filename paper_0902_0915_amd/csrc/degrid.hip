@@ -54,7 +54,7 @@ Status launch_degrid_npol(Instance &I, DegridArgs &a, hipStream_t s) {
         lds += sizeof(float2) * (size_t)I.nant;
     }
     if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "degrid tile needs %zu B of LDS", lds);
-    hipLaunchKernelGGL(k_degrid<NPOL>, dim3(I.nwork), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_degrid<NPOL>, dim3(I.nwork), dim3(degrid_threads(I.nkept, I.nwork)), lds, s, a);
     MWG_HIP(hipGetLastError());
     return Status::Ok();
 }

@@ -16,6 +16,13 @@ struct DegridArgs {
     int nx, ny, T, ntx, W, O, nant, ant_in_lds;
 };
 
+// Threads per degridder workgroup for work items of (on average) groups_per_item groups: one
+// thread per group, 64 to 256, so that sparse plans do not leave most of each workgroup idle.
+inline int degrid_threads(int64_t groups, int64_t items) {
+    const int64_t avg = items > 0 ? groups / items : 0;
+    return avg <= 64 ? 64 : (avg <= 128 ? 128 : 256);
+}
+
 // One workgroup grids-back one work item: stage its haloed grid tile in LDS, then one
 // thread per group gathers the footprint. smem is the workgroup's dynamic LDS.
 template <int NPOL>
