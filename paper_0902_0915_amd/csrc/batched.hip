@@ -346,6 +346,28 @@ Status refresh_desc(Batch &B, const void *const *vis, const void *const *gains, 
 Status batch_prepare(Plan &P, hipStream_t s) {
     P.batch = nullptr;
     if (P.inst.size() < 2) return Status::Ok();
+    // Sparse batches (fewer than 64 kept groups per non-empty 8 x 8 tile on average) take
+    // 16 x 16 tiles: a quarter of the work items, each staging and flushing less halo per
+    // group. The batch as a whole still has items enough to fill the chip, which one sparse
+    // instance on its own does not, so single-instance plans keep 8 x 8.
+    {
+        bool retile = true;
+        int64_t kept = 0, tiles = 0;
+        for (const Instance *I : P.inst) {
+            retile = retile && !I->stacks && !I->tile_fixed && I->L.variant == 4 && I->L.flush == 2 &&
+                     I->L.tile == 8 && I->L.schedule == 1 &&
+                     wavetiles_lds(I->npol, 16, I->W, I->O, I->L.wg_waves) <= 160 * 1024;
+            kept += I->nkept;
+            tiles += I->ntiles_nonempty;
+        }
+        if (retile && tiles > 0 && kept < 64 * tiles) {
+            for (Instance *I : P.inst) {
+                Launch L = I->L;
+                L.tile = 16;
+                MWG_TRY(rebuild_schedule(*I, L, s));
+            }
+        }
+    }
     const Instance &I0 = *P.inst[0];
     for (const Instance *I : P.inst) {
         if (I->stacks || I->npol != I0.npol || I->W != I0.W || I->O != I0.O || I->L.variant != 4 ||

@@ -89,6 +89,7 @@ struct Instance {
     int64_t nkept = 0, nflagged = 0, noutside = 0;
     // launch
     Launch L;
+    bool tile_fixed = false;  // the caller chose the tile (or asked the autotuner)
     int ntx = 0, nty = 0, ntiles_nonempty = 0, nwork = 0;
     int max_work_groups = 0;  // largest work item
     int sorted_tile = 0, sorted_order = 0;   // the (tile, order) perm is currently sorted by

@@ -68,10 +68,24 @@ def test_batched_grid_parity_and_graph_replays(mw, jobs):
 def test_batched_grid_matches_single_instance_plans(mw, jobs):
     with mw.Plan(_specs(mw, jobs, with_ants=False)) as plan:
         batched = [to_host(g) for g in plan.grid([to_dev(j.vis) for j in jobs])]
-    for j, b in zip(jobs, batched):
-        with mw.Plan(mw.InstanceSpec.from_workload(j, with_ants=False)) as single:
+        tiles = [plan.info(k)["tile"] for k in range(len(jobs))]
+    # these jobs are sparse (a few groups per 8 x 8 tile): the batch takes 16 x 16 tiles
+    assert set(tiles) == {16}
+    for j, b, t in zip(jobs, batched, tiles):
+        with mw.Plan(mw.InstanceSpec.from_workload(j, with_ants=False), tuning=dict(tile=t)) as single:
             s = to_host(single.grid(to_dev(j.vis)))
         np.testing.assert_array_equal(s, b)  # identical arithmetic, identical order
+
+
+def test_dense_batch_keeps_8x8_tiles_and_a_set_tile_is_kept(mw):
+    dense = synth.batched_jobs(seed=4003, njobs=2, nmin=60000, nmax=80000, sizes=(256,), nant=64,
+                               nchan=8, ntime=2)
+    with mw.Plan(_specs(mw, dense, with_ants=False)) as plan:
+        assert {plan.info(k)["tile"] for k in range(2)} == {8}
+    sparse = synth.batched_jobs(seed=4002, njobs=3, nmin=2000, nmax=30000, sizes=(512,), nant=64,
+                                nchan=8, ntime=2)
+    with mw.Plan(_specs(mw, sparse, with_ants=False), tuning=dict(tile=8)) as plan:
+        assert {plan.info(k)["tile"] for k in range(3)} == {8}
 
 
 def test_batched_degrid_with_gains_and_grad(mw, jobs):
