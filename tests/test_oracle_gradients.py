@@ -20,40 +20,44 @@ def subset():
     return sub
 
 
-def _image(orc, wl, pos, keep, vis, gains):
+def _image(orc, wl, pos, keep, vis, gains, correct):
     G = orc.grid(pos, keep, vis, wl.nx, wl.ny, 7, 8, nchan=wl.nchan, gains=gains, ant1=wl.ant1,
                  ant2=wl.ant2)
-    return orc.image(G, W=7)
+    return orc.image(G, W=7, correct=correct)
 
 
-def _loss_diff(orc, wl, pos, keep, vp, gp, vm, gm, target):
+def _loss_diff(orc, wl, pos, keep, vp, gp, vm, gm, target, correct):
     """L(+) - L(-) for L = sum |I - T|^2, through the exact identity
     |a - T|^2 - |b - T|^2 = Re(conj(a - b) (a + b - 2T)), which avoids subtracting two large
     losses (the loss is ~1e14 here, so the plain difference loses ~6 digits)."""
-    a = _image(orc, wl, pos, keep, vp, gp)
-    b = _image(orc, wl, pos, keep, vm, gm)
+    a = _image(orc, wl, pos, keep, vp, gp, correct)
+    b = _image(orc, wl, pos, keep, vm, gm, correct)
     return float(np.sum((np.conj(a - b) * (a + b - 2.0 * target)).real))
 
 
+@pytest.mark.parametrize("correct", [True, False], ids=["corrected", "uncorrected"])
 @pytest.mark.parametrize("step,tol,vstep,vtol", [(1e-6, 2e-6, 1e-3, 1e-6),
                                                  (1e-3, 1e-8, 1.0, 1e-8)])
-def test_gradients_match_central_differences(orc, subset, step, tol, vstep, vtol):
+def test_gradients_match_central_differences(orc, subset, step, tol, vstep, vtol, correct):
     # Along any one real coordinate of one gain (no autocorrelations, so each baseline holds
     # a given antenna once) or of one visibility, the image is affine and the loss exactly
     # quadratic: central differences carry no truncation error, only rounding, which scales
     # as 1/step. The corrected image's corner pixels are amplified ~2.7e7 by the correction,
     # so at step 1e-6 rounding alone reaches ~1e-6 relative; at 1e-3 it is ~1e-9. One
     # visibility moves the image ~1e4 times less than one gain, so its steps are larger.
+    # Both loss forms are pinned: on the corrected image and on the uncorrected transform
+    # (the form the GPU gradient tests use), whose adjoint must then skip the correction too.
     wl = subset
     assert wl.ngroups == 120 * 8 * 4
     pos, keep, _ = orc.positions(wl.uvw, wl.freq, wl.nx, wl.ny, wl.du, wl.dv, 7, 8)
     assert keep.all()
     vis = wl.vis.astype(np.complex128)
-    true_img = orc.image(orc.grid(pos, keep, vis, wl.nx, wl.ny, 7, 8, nchan=wl.nchan), W=7)
+    true_img = orc.image(orc.grid(pos, keep, vis, wl.nx, wl.ny, 7, 8, nchan=wl.nchan), W=7,
+                         correct=correct)
     gains = wl.gains.astype(np.complex128)
     loss, img, grad_v, grad_g = orc.loss_and_grads(pos, keep, vis, gains, wl.ant1, wl.ant2,
                                                    true_img, wl.nx, wl.ny, 7, 8,
-                                                   nchan=wl.nchan)
+                                                   nchan=wl.nchan, correct=correct)
     assert loss > 0
     fd = np.zeros(len(gains), dtype=np.complex128)
     for a in range(len(gains)):
@@ -61,7 +65,7 @@ def test_gradients_match_central_differences(orc, subset, step, tol, vstep, vtol
             gp, gm = gains.copy(), gains.copy()
             gp[a] += step * unit
             gm[a] -= step * unit
-            d = _loss_diff(orc, wl, pos, keep, vis, gp, vis, gm, true_img) / (2 * step)
+            d = _loss_diff(orc, wl, pos, keep, vis, gp, vis, gm, true_img, correct) / (2 * step)
             fd[a] += d * unit
     scale = np.max(np.abs(grad_g))
     assert np.max(np.abs(fd - grad_g)) <= tol * scale
@@ -74,7 +78,8 @@ def test_gradients_match_central_differences(orc, subset, step, tol, vstep, vtol
             vp, vm = vis.copy(), vis.copy()
             vp[k, 0] += vstep * unit
             vm[k, 0] -= vstep * unit
-            d = _loss_diff(orc, wl, pos, keep, vp, gains, vm, gains, true_img) / (2 * vstep)
+            d = _loss_diff(orc, wl, pos, keep, vp, gains, vm, gains, true_img,
+                           correct) / (2 * vstep)
             fdv[j] += d * unit
     scale_v = np.max(np.abs(grad_v[idx, 0]))
     assert np.max(np.abs(fdv - grad_v[idx, 0])) <= vtol * scale_v
