@@ -317,11 +317,13 @@ def image_adjoint(img, W=7, correct=True):
 # forward model g1 * conj(g2) * V and the gradients flow back through the adjoints.
 # ---------------------------------------------------------------------------------------------
 def loss_and_grads(pos, keep, vis, gains, ant1, ant2, target, nx, ny, W, O, nchan=1,
-                   weights=None, correct=True, nthreads=None):
+                   weights=None, correct=True, nthreads=None, mask=None):
     """L = sum |image(grid(g1 conj(g2) V)) - target|^2, with dL/dV and dL/dg.
 
-    grad_I = 2 (I - target); grad_G = image_adjoint(grad_I); gamma = degrid(grad_G) without
-    gains; grad_V = conj(g1) g2 gamma;
+    mask: optional real [ny, nx] array of 0/1; the sum then runs over the pixels it selects
+    (L = sum mask |I - target|^2).
+    grad_I = 2 mask (I - target); grad_G = image_adjoint(grad_I); gamma = degrid(grad_G)
+    without gains; grad_V = conj(g1) g2 gamma;
     grad_g[a] = sum_{a1 = a} g2 conj(V) gamma + sum_{a2 = a} g1 V conj(gamma) (summed over pols).
     """
     vis2 = np.asarray(vis, dtype=np.complex128)
@@ -334,6 +336,8 @@ def loss_and_grads(pos, keep, vis, gains, ant1, ant2, target, nx, ny, W, O, ncha
              ant1=ant1, ant2=ant2, nthreads=nthreads)
     img = image(G, W=W, correct=correct)
     diff = img - target
+    if mask is not None:
+        diff = diff * np.asarray(mask, dtype=np.float64)
     loss = float(np.sum(np.abs(diff) ** 2))
     grad_img = 2.0 * diff
     grad_grid = image_adjoint(grad_img, W=W, correct=correct)
