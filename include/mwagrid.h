@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MW_ABI_VERSION 2
+#define MW_ABI_VERSION 3
 
 typedef enum {
     MW_OK = 0,
@@ -105,11 +105,17 @@ typedef struct {
     int32_t flush;      /* 1 = atomic adds of each finished tile into the zeroed grid,
                            2 = tiles to a scratch buffer, then a merge pass writes the grid
                            (with variant 4 the result is then bit-reproducible) */
-    int32_t autotune;   /* 1 = time candidate launches (tile, waves, split, schedule, flush)
-                           on this plan's own positions and keep the fastest; if the
-                           environment variable MW_TUNE_CACHE names a file, results are
-                           read from and appended to it, keyed by grid size, W, O, npol
-                           and the order of magnitude of the visibility count */
+    int32_t autotune;   /* 1 = time candidate launches (tile, waves, split, schedule; the
+                           default launch first) on this plan's own positions and keep the
+                           fastest. Non-zero fields above stay fixed; flush stays 2 (the
+                           bit-reproducible merge) unless set to 1 here. A plan of several
+                           instances that can share one launch (same npol, W, O, built-in
+                           kernel) is timed as a whole batched sequence, one launch for all
+                           its instances, and stays batched. If the environment variable
+                           MW_TUNE_CACHE names a file, results are read from and appended to
+                           it, keyed by grid size, W, O, npol and the order of magnitude of
+                           the visibility count (for batches: the instance count, total
+                           visibilities and total cells) */
     int32_t schedule;   /* work-item order: 1 = largest first, 2 = Z-order of tiles split into
                            8 equal-work chunks, one per XCD (variant 4 only), 3 = largest
                            first, each item shared by up to wg_waves waves of one workgroup
@@ -123,6 +129,9 @@ typedef struct {
     int32_t tile, split, wg_waves, order, variant, flush; /* the launch actually chosen */
     int32_t schedule;
     int64_t plan_bytes;           /* device memory owned by the plan for this instance */
+    int32_t batched;              /* 1: the plan's instances run as one batched launch
+                                     sequence (replayed from a captured graph); 0: one by one */
+    int32_t pad0;
 } mw_plan_stats;
 
 /*

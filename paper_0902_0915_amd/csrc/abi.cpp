@@ -139,14 +139,16 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
             mwg::Instance *I = new mwg::Instance();
             P->inst.push_back(I);
             mwg::Status s = mwg::build_instance(*I, inst[i], tuning, st);
-            if (s.ok() && tuning && tuning->autotune) s = mwg::autotune(*I, st);
             if (!s.ok()) {
                 destroy_plan(P);
                 return fail(s);
             }
         }
-        if (ninst > 1) {
-            mwg::Status s = mwg::batch_prepare(*P, st);
+        {
+            // the tuner forms (and times) the batch itself; otherwise form it here
+            mwg::Status s = (tuning && tuning->autotune) ? mwg::autotune_plan(*P, *tuning, st)
+                            : ninst > 1                  ? mwg::batch_prepare(*P, st)
+                                                         : mwg::Status::Ok();
             if (!s.ok()) {
                 destroy_plan(P);
                 return fail(s);
@@ -291,6 +293,7 @@ mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out) {
             out->flush = I.L.flush;
             out->schedule = I.L.schedule;
         }
+        out->batched = P->batch ? 1 : 0;
         return ok();
     } catch (...) {
         return fail(MW_ERR_HIP, "unexpected exception in mw_plan_info");

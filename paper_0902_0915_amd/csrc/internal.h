@@ -199,6 +199,8 @@ Status batch_degrid(Plan &P, const void *const *grid, const void *const *gains,
 void batch_release(Plan &P);
 
 // tuner.cpp
-Status autotune(Instance &I, hipStream_t s);
+Status autotune(Instance &I, const mw_tuning &user, hipStream_t s);
+Status autotune_plan(Plan &P, const mw_tuning &user, hipStream_t s);
+bool batch_compatible(const Plan &P);
 
 } // namespace mwg

@@ -921,7 +921,7 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     }
     Launch L;
     MWG_TRY(resolve_launch(I, tuning, &L));
-    I.tile_fixed = tuning && (tuning->tile != 0 || tuning->autotune != 0);
+    I.tile_fixed = tuning && tuning->tile != 0;
     MWG_TRY(rebuild_schedule(I, L, s));
     if (I.stacks) MWG_TRY(build_stack_schedule(I, L, s));
 

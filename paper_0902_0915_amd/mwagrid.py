@@ -49,7 +49,7 @@ class MwPlanStats(ctypes.Structure):
     _fields_ = [("ngroups", _i64), ("nkept", _i64), ("nflagged", _i64), ("noutside", _i64),
                 ("ntiles", _i32), ("nwork", _i32), ("tile", _i32), ("split", _i32),
                 ("wg_waves", _i32), ("order", _i32), ("variant", _i32), ("flush", _i32),
-                ("schedule", _i32), ("plan_bytes", _i64)]
+                ("schedule", _i32), ("plan_bytes", _i64), ("batched", _i32), ("pad0", _i32)]
 
 
 _PP = ctypes.POINTER(ctypes.c_void_p)

@@ -131,5 +131,43 @@ def test_mixed_instances_fall_back_to_per_instance_launches(mw, jobs):
     with mw.Plan([mw.InstanceSpec.from_workload(a, with_ants=False),
                   mw.InstanceSpec.from_workload(b5, with_ants=False)]) as plan:
         out = plan.grid([to_dev(a.vis), to_dev(b5.vis)])
+        assert plan.info(-1)["batched"] == 0
     assert nl2(to_host(out[0]), _oracle_grid(a, a.vis)[0]) <= TOL
     assert nl2(to_host(out[1]), _oracle_grid(b5, b5.vis)[0]) <= TOL
+
+
+def test_autotune_tunes_the_batch_as_a_whole(mw, jobs, tmp_path, monkeypatch):
+    """autotune on a multi-instance plan times the batched sequence itself: every instance
+    takes the same launch, the plan stays batched, and the grids match the oracle. A cached
+    result is taken by the next plan over the same jobs without a new search."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("MW_TUNE_CACHE", str(cache))
+    refs = [_oracle_grid(j, j.vis)[0] for j in jobs]
+    with mw.Plan(_specs(mw, jobs, with_ants=False), tuning=dict(autotune=1)) as plan:
+        assert plan.info(-1)["batched"] == 1
+        launches = {tuple(plan.info(k)[f] for f in ("tile", "wg_waves", "variant", "flush", "schedule"))
+                    for k in range(len(jobs))}
+        out = plan.grid([to_dev(j.vis) for j in jobs])
+        back = plan.degrid(out)
+    assert len(launches) == 1
+    assert next(iter(launches))[3] == 2  # the bit-reproducible merge flush
+    for j, o, b, r in zip(jobs, out, back, refs):
+        assert nl2(to_host(o), r) <= TOL
+        pos, keep, _ = orc.positions(j.uvw, j.freq, j.nx, j.ny, j.du, j.dv, j.W, j.O, flags=j.flags)
+        assert nl2(to_host(b), orc.degrid(pos, keep, to_host(o), j.W, j.O, nchan=j.nchan)) <= TOL
+    lines = cache.read_text().strip().splitlines()
+    assert len(lines) == 1 and "/batch7/" in lines[0]
+    with mw.Plan(_specs(mw, jobs, with_ants=False), tuning=dict(autotune=1)) as plan2:
+        assert plan2.info(-1)["batched"] == 1
+        again = {tuple(plan2.info(k)[f] for f in ("tile", "wg_waves", "variant", "flush", "schedule"))
+                 for k in range(len(jobs))}
+        out2 = plan2.grid([to_dev(j.vis) for j in jobs])
+    assert again == launches
+    assert len(cache.read_text().strip().splitlines()) == 1
+    for o, r in zip(out2, refs):
+        assert nl2(to_host(o), r) <= TOL
+
+
+def test_plain_batch_reports_batched(mw, jobs):
+    with mw.Plan(_specs(mw, jobs[:3], with_ants=False)) as plan:
+        assert plan.info(-1)["batched"] == 1

@@ -148,6 +148,31 @@ def test_grid_parity_variants(mw, npol, W, variant):
     assert nl2(got, ref) <= TOL, nl2(got, ref)
 
 
+@pytest.mark.parametrize("W,O,npol", [(1, 8, 1), (1, 1, 4), (9, 8, 1), (11, 8, 2), (13, 8, 1),
+                                      (15, 8, 4), (7, 1, 1), (7, 3, 4), (7, 16, 1), (5, 16, 2),
+                                      (15, 16, 1), (3, 3, 2)])
+def test_grid_degrid_parity_supports_and_oversampling(mw, W, O, npol):
+    """Every support the ABI accepts (odd W, 1...15) and oversampling at its edges (O = 1,
+    odd O = 3, O = 16: the 4-bit phase fields at their top), each on the default launch,
+    grid and adjoint."""
+    rng = np.random.default_rng(W * 100 + O * 10 + npol)
+    wl = synth.mwa_scale(seed=2010 + W + O, nant=40, nchan=4, ntime=2, npol=npol, n=256, nsrc=10,
+                         W=W, O=O)
+    pos, keep, _ = oracle_positions(wl)
+    assert keep.sum() > 1000
+    ref = orc.grid(pos, keep, wl.vis, wl.nx, wl.ny, W, O, nchan=wl.nchan)
+    Gy = (rng.standard_normal((npol, wl.ny, wl.nx)) + 1j * rng.standard_normal((npol, wl.ny, wl.nx)))
+    Gy = Gy.astype(np.complex64)
+    ref_back = orc.degrid(pos, keep, Gy, W, O, nchan=wl.nchan)
+    with _plan(mw, wl, with_ants=False) as plan:
+        got = to_host(plan.grid(to_dev(wl.vis)))
+        back = to_host(plan.degrid(to_dev(Gy)))
+        info = plan.info(0)
+    assert nl2(got, ref) <= TOL, (info, nl2(got, ref))
+    assert nl2(back, ref_back) <= TOL, (info, nl2(back, ref_back))
+    assert np.all(back[~keep] == 0)
+
+
 @pytest.mark.parametrize("tuning", [None, dict(tile=64, wg_waves=4), dict(variant=3),
                                     dict(flush=2), dict(variant=1)], ids=str)
 def test_grid_parity_tiny_1pol(mw, tiny, tuning):
@@ -335,6 +360,38 @@ def test_autograd_matches_oracle_gradients(mw, correct):
         loss = torch.sum(torch.abs(img - tgt) ** 2)
         loss.backward()
         assert nl2(to_host(img), img_ref) <= TOL
+        assert abs(loss.item() - loss_ref) <= 1e-4 * loss_ref
+        assert nl2(to_host(vis.grad), gv_ref) <= GTOL
+        assert nl2(to_host(g.grad), gg_ref) <= GTOL
+
+
+def test_autograd_corrected_masked_loss_matches_oracle(mw):
+    """The loss on the convolution-corrected image, summed over the inner half of the field
+    (where the correction amplifies rounding at most ~15-fold): the backward then divides by
+    the correction in the image adjoint, which the uncorrected form never exercises."""
+    import torch
+    from paper_0902_0915_amd.mwagrid import grid_image
+    wl = synth.differentiable(nant=32, nchan=4, ntime=2, n=256, nsrc=8)
+    pos, keep, _ = oracle_positions(wl)
+    V = wl.vis.astype(np.complex128)
+    target = orc.image(orc.grid(pos, keep, V, wl.nx, wl.ny, 7, 8, nchan=wl.nchan), W=7,
+                       correct=True)
+    mask = np.zeros((wl.ny, wl.nx))
+    mask[wl.ny // 4:3 * wl.ny // 4, wl.nx // 4:3 * wl.nx // 4] = 1.0
+    gains = wl.gains.astype(np.complex128)
+    loss_ref, img_ref, gv_ref, gg_ref = orc.loss_and_grads(
+        pos, keep, V, gains, wl.ant1, wl.ant2, target, wl.nx, wl.ny, 7, 8, nchan=wl.nchan,
+        correct=True, mask=mask)
+    with _plan(mw, wl) as plan:
+        vis = to_dev(wl.vis).requires_grad_(True)
+        g = to_dev(wl.gains).requires_grad_(True)
+        img = grid_image(vis, g, plan, correct=True)
+        tgt = to_dev(target.astype(np.complex64))
+        m = to_dev(mask.astype(np.float32))
+        loss = torch.sum(m * torch.abs(img - tgt) ** 2)
+        loss.backward()
+        q = slice(wl.nx // 4, 3 * wl.nx // 4)
+        assert nl2(to_host(img)[q, q], img_ref[q, q]) <= TOL
         assert abs(loss.item() - loss_ref) <= 1e-4 * loss_ref
         assert nl2(to_host(vis.grad), gv_ref) <= GTOL
         assert nl2(to_host(g.grad), gg_ref) <= GTOL
