@@ -85,7 +85,7 @@ struct PosArgs {
     const int32_t *kidx;   // stacks: kernel of each group
     const int32_t *ksup;   // stacks: support of each kernel
     uint32_t *pos;
-    unsigned long long *counts; // kept, flagged, outside
+    uint32_t *blk_counts;  // [gridDim.x][3]: kept, flagged, outside of each block
 };
 
 __global__ void k_positions(PosArgs a) {
@@ -123,13 +123,42 @@ __global__ void k_positions(PosArgs a) {
         }
         a.pos[g] = packed;
     }
-    // one atomic per wave and category
+    // Counts per block, no atomics: every wave stores its three ballot counts in LDS, the
+    // first thread sums them and writes the block's entry (a later kernel sums the blocks).
+    // Atomics from every wave on one counter serialise the waves.
+    __shared__ uint32_t wc[kBlock / 64][3];
     const unsigned long long k0 = __ballot(status == 0), k1 = __ballot(status == 1),
                              k2 = __ballot(status == 2);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (k0) atomicAdd(&a.counts[0], (unsigned long long)__popcll(k0));
-        if (k1) atomicAdd(&a.counts[1], (unsigned long long)__popcll(k1));
-        if (k2) atomicAdd(&a.counts[2], (unsigned long long)__popcll(k2));
+        wc[w][0] = (uint32_t)__popcll(k0);
+        wc[w][1] = (uint32_t)__popcll(k1);
+        wc[w][2] = (uint32_t)__popcll(k2);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t t = 0;
+        for (int k = 0; k < kBlock / 64; k++) t += wc[k][threadIdx.x];
+        a.blk_counts[(int64_t)blockIdx.x * 3 + threadIdx.x] = t;
+    }
+}
+
+// Sums the per-block counts: one workgroup, out[c] = sum over blocks of cnt[b][c].
+__global__ void k_sum_counts(const uint32_t *cnt, int64_t nblocks, unsigned long long *out) {
+    __shared__ unsigned long long part[kBlock / 64][3];
+    unsigned long long t[3] = {0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int c = 0; c < 3; c++) t[c] += cnt[b * 3 + c];
+    for (int c = 0; c < 3; c++) {
+        unsigned long long v = t[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0;
+        for (int k = 0; k < kBlock / 64; k++) v += part[k][threadIdx.x];
+        out[threadIdx.x] = v;
     }
 }
 
@@ -297,52 +326,70 @@ __global__ void k_scan_add(uint32_t *data, int64_t n, const uint32_t *sums) {
         if (base + j < n) data[base + j] += add;
 }
 
-Status scan_exclusive(uint32_t *data, int64_t n, hipStream_t s) {
+// Words of scratch scan_exclusive needs for n items: one partial sum per block at every
+// level of the recursion.
+int64_t scan_ws_words(int64_t n) {
+    int64_t w = 0;
+    while (n > 1) {
+        n = (n + kScanChunk - 1) / kScanChunk;
+        w += n;
+    }
+    return w + 1;
+}
+
+// Exclusive scan in place; ws holds scan_ws_words(n) words and must outlive the kernels
+// (enqueued on s, no synchronisation here).
+Status scan_exclusive(uint32_t *data, int64_t n, uint32_t *ws, hipStream_t s) {
     if (n <= 0) return Status::Ok();
     const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
-    Tmp sums;
-    MWG_TRY(sums.alloc(sizeof(uint32_t) * nb));
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n,
-                       sums.as<uint32_t>());
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n, ws);
     MWG_HIP(hipGetLastError());
     if (nb > 1) {
-        MWG_TRY(scan_exclusive(sums.as<uint32_t>(), nb, s));
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n,
-                           sums.as<uint32_t>());
+        MWG_TRY(scan_exclusive(ws, nb, ws + nb, s));
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kBlock), 0, s, data, n, ws);
         MWG_HIP(hipGetLastError());
     }
-    // sums must outlive the kernels that read it
-    MWG_HIP(hipStreamSynchronize(s));
     return Status::Ok();
 }
 
-// Sorts (keys, implicit index) by the low keybits bits; result in keys_out/vals_out.
+Status scan_exclusive(uint32_t *data, int64_t n, hipStream_t s) {
+    Tmp ws;
+    MWG_TRY(ws.alloc(4 * (size_t)scan_ws_words(n)));
+    MWG_TRY(scan_exclusive(data, n, ws.as<uint32_t>(), s));
+    MWG_HIP(hipStreamSynchronize(s));  // ws must outlive the kernels
+    return Status::Ok();
+}
+
+// Sorts (keys, implicit index) by the low keybits bits; result in keys_out/vals_out. The
+// histogram and scan scratch are allocated once for all passes; one synchronisation at
+// the end.
 Status radix_sort(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *vals_alt,
                   int64_t n, int keybits, uint32_t **keys_out, uint32_t **vals_out,
                   hipStream_t s, const uint32_t *vals_init = nullptr) {
     const int nblocks = (int)((n + kSortChunk - 1) / kSortChunk);
-    Tmp hist;
-    MWG_TRY(hist.alloc(sizeof(uint32_t) * 256 * (size_t)std::max(nblocks, 1)));
+    const int64_t nh = (int64_t)256 * std::max(nblocks, 1);
+    Tmp ws;
+    MWG_TRY(ws.alloc(4 * (size_t)(nh + scan_ws_words(nh))));
+    uint32_t *hist = ws.as<uint32_t>(), *sws = hist + nh;
     uint32_t *kin = keys, *kout = keys_alt, *vout = vals;
     const uint32_t *vin = vals_init;
     const int passes = (keybits + 7) / 8;
+    if (passes == 0) return make_error(MW_ERR_UNSUPPORTED, "empty sort key");
     for (int p = 0; p < passes; p++) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift,
-                           hist.as<uint32_t>(), nblocks);
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kBlock), 0, s, kin, n, shift, hist, nblocks);
         MWG_HIP(hipGetLastError());
-        MWG_TRY(scan_exclusive(hist.as<uint32_t>(), (int64_t)256 * nblocks, s));
+        MWG_TRY(scan_exclusive(hist, nh, sws, s));
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kBlock), 0, s, kin, vin, kout, vout,
-                           hist.as<uint32_t>(), n, shift, nblocks);
+                           hist, n, shift, nblocks);
         MWG_HIP(hipGetLastError());
         std::swap(kin, kout);
         vin = vout;
         vout = (vout == vals) ? vals_alt : vals;
     }
-    if (passes == 0) return make_error(MW_ERR_UNSUPPORTED, "empty sort key");
     *keys_out = kin;
     *vals_out = const_cast<uint32_t *>(vin); // after a pass vin is vals or vals_alt
-    MWG_HIP(hipStreamSynchronize(s));
+    MWG_HIP(hipStreamSynchronize(s));  // the scratch must outlive the kernels
     return Status::Ok();
 }
 
@@ -847,9 +894,10 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     // A1: positions
     MWG_TRY(I.arena.alloc(&p, 4 * (size_t)ng));
     I.pos = (uint32_t *)p;
+    const int64_t pos_blocks = std::max<int64_t>(1, (int64_t)grid1d(ng));
     Tmp counts;
-    MWG_TRY(counts.alloc(3 * sizeof(unsigned long long)));
-    MWG_TRY(launch_fill_u32(counts.as<uint32_t>(), 6, 0, s));
+    MWG_TRY(counts.alloc(3 * sizeof(unsigned long long) + 12 * (size_t)pos_blocks));
+    MWG_TRY(launch_fill_u32(counts.as<uint32_t>(), 6 + 3 * pos_blocks, 0, s));
     PosArgs a;
     a.ngroups = ng;
     a.nchan = I.nchan;
@@ -866,9 +914,12 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     a.kidx = kidx;
     a.ksup = ksup;
     a.pos = I.pos;
-    a.counts = counts.as<unsigned long long>();
+    a.blk_counts = counts.as<uint32_t>() + 6;
     if (ng > 0) {
         hipLaunchKernelGGL(k_positions, dim3(grid1d(ng)), dim3(kBlock), 0, s, a);
+        MWG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(kBlock), 0, s, a.blk_counts, pos_blocks,
+                           counts.as<unsigned long long>());
         MWG_HIP(hipGetLastError());
     }
     unsigned long long hc[3] = {0, 0, 0};
