@@ -352,3 +352,54 @@ def loss_and_grads(pos, keep, vis, gains, ant1, ant2, target, nx, ny, W, O, ncha
     np.add.at(grad_g, ant1[rows], term1)
     np.add.at(grad_g, ant2[rows], term2)
     return loss, img, grad_vis, grad_g
+
+
+# ---------------------------------------------------------------------------------------------
+# Stokes conversion (Section 2.1: the instrumental-polarisation images are converted into
+# Stokes parameters by a 4 x 4 matrix that depends on time and on the position on the sky
+# relative to the instrument, computed for every pixel; Table 1, "Stokes Conversion").
+# ---------------------------------------------------------------------------------------------
+# Coherency vector (XX, XY, YX, YY) of Stokes (I, Q, U, V) for linear feeds:
+# XX = I + Q, XY = U + iV, YX = U - iV, YY = I - Q.
+STOKES_TO_COHERENCY = np.array([[1, 1, 0, 0],
+                                [0, 0, 1, 1j],
+                                [0, 0, 1, -1j],
+                                [1, -1, 0, 0]], dtype=np.complex128)
+
+
+def stokes(images, jones=None, pixels=None):
+    """Stokes images (I, Q, U, V) from the four instrumental-polarisation transforms.
+
+    images: complex [4, ny, nx] in the order XX, XY, YX, YY, as ``image`` returns them from
+    visibilities gridded without their Hermitian mirror. The mirrored samples (conj(V) at -u;
+    for a cross product XY the mirror of YX) would add the complex conjugate image, so the
+    instrumental image of the full coherency is, per pixel,
+        e = (2 Re XX, XY + conj(YX), YX + conj(XY), 2 Re YY).
+    jones: complex [ny, nx, 2, 2] (the instrument's response J toward each pixel at the
+    snapshot's time: measured coherency = J C J^H), or None for ideal feeds (J = 1).
+    Per pixel the 4 x 4 matrix M = S^-1 (J^-1 kron conj(J^-1)), with S the Stokes-to-coherency
+    matrix above, maps e to (I, Q, U, V). Returns float64 [4, ny, nx] (the real parts; the
+    imaginary parts vanish for Hermitian e). pixels: optional int [k, 2] of (x, y); then only
+    those pixels are converted and the result is float64 [4, k].
+    """
+    z = np.asarray(images, dtype=np.complex128)
+    npol, ny, nx = z.shape
+    if npol != 4:
+        raise ValueError("Stokes conversion needs the 4 instrumental polarisations")
+    if pixels is None:
+        yy, xx = np.divmod(np.arange(ny * nx), nx)
+    else:
+        px = np.asarray(pixels, dtype=np.int64)
+        xx, yy = px[:, 0], px[:, 1]
+    Sinv = np.linalg.inv(STOKES_TO_COHERENCY)
+    out = np.empty((4, len(xx)), dtype=np.complex128)
+    for k, (x, y) in enumerate(zip(xx, yy)):
+        c = z[:, y, x]
+        e = np.array([2.0 * c[0].real, c[1] + np.conj(c[2]), c[2] + np.conj(c[1]), 2.0 * c[3].real])
+        if jones is None:
+            M = Sinv
+        else:
+            Ji = np.linalg.inv(np.asarray(jones[y, x], dtype=np.complex128))
+            M = Sinv @ np.kron(Ji, np.conj(Ji))
+        out[:, k] = M @ e
+    return out.real if pixels is not None else out.real.reshape(4, ny, nx)
