@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the kernel-stack and differentiable workloads")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="visibility groups (of 4 pols) in the oracle's timed sample "
                          "(0 = the whole workload, about 10 s on 16 host cores)")
@@ -84,6 +86,7 @@ def parse():
 
 
 def timed(fn, steps, stream):
+    """Mean event time and mean wall time per call of fn over ``steps`` back-to-back calls."""
     import torch
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -96,6 +99,23 @@ def timed(fn, steps, stream):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / steps, wall * 1e3 / steps
+
+
+def percentiles(fn, steps, stream):
+    """Per-call event times of fn (each call bracketed by its own events, still back to back
+    on the stream): median, p10 and p90 in ms."""
+    import numpy as np
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(steps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    t = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return {"median": round(float(np.median(t)), 4), "p10": round(float(np.percentile(t, 10)), 4),
+            "p90": round(float(np.percentile(t, 90)), 4), "n": steps}
 
 
 def main():
@@ -160,6 +180,8 @@ def main():
     log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
     ev_ms, wall_ms = timed(step, args.steps, stream)
     log(f"step: {ev_ms:.3f} ms (events), {wall_ms:.3f} ms (wall)")
+    step_pct = percentiles(step, args.steps, stream)
+    log(f"step percentiles: {step_pct}")
     fb_ms, _ = timed(fwd_bwd, max(1, args.steps // 2), stream)
     log(f"forward + backward: {fb_ms:.3f} ms")
     # dominant kernel: the library's events around its own gridder launch, on its stream
@@ -203,6 +225,32 @@ def main():
            "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
            "alg_flop_per_launch": alg_flop}
 
+    # Stokes conversion of the step's four corrected images with a per-pixel instrument
+    # response (2048^2): reads 32 B of images and 32 B of Jones matrix per pixel, writes 16 B.
+    jones = torch.from_numpy(synth.jones_field(wl.nx, wl.ny, hour_angle=0.1)).cuda()
+    stokes_out = torch.empty((4, wl.ny, wl.nx), dtype=torch.float32, device="cuda")
+    plan.stokes(img, jones, out=stokes_out)
+    st_pct = percentiles(lambda: plan.stokes(img, jones, out=stokes_out), args.steps, stream)
+    st_bytes = wl.nx * wl.ny * (32 + 32 + 16)
+    stokes = {"workload": f"{wl.ny}x{wl.nx} pixels x 4 polarisations, per-pixel Jones matrices",
+              "ms": st_pct, "alg_bytes": st_bytes,
+              "achieved_gbs": round(st_bytes / (st_pct["median"] * 1e-3) / 1e9, 1),
+              "frac_hbm": round(st_bytes / (st_pct["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"stokes: {stokes}")
+    del jones, stokes_out
+
+    # Plan for new uvw (a new snapshot) plus one grid call.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with mwagrid.Plan(spec, tuning=tuning or None) as p2:
+        p2.grid(vis, out=grid)
+        torch.cuda.synchronize()
+        plan_grid_ms = (time.perf_counter() - t0) * 1e3
+    log(f"plan + one grid: {plan_grid_ms:.1f} ms")
+
+    stacks = None if args.no_extra else bench_stacks(mwagrid, synth, stream, args.steps)
+    diff = None if args.no_extra else bench_differentiable(mwagrid, synth, stream, args.steps)
+
     batched = None
     if not args.no_batched:
         batched = bench_batched(mwagrid, synth, stream, max(3, args.steps // 4))
@@ -227,13 +275,87 @@ def main():
         "grid_mvis_s": round(nvis / ((kern_ms + merge_ms) * 1e-3) / 1e6, 1),
         "merge_ms": round(merge_ms, 4),
         "step_event_ms": round(ev_ms, 4),
+        "step_ms_percentiles": step_pct,
         "plan_ms": round(plan_ms, 1),
+        "plan_plus_grid_ms": round(plan_grid_ms, 1),
         "fwd_bwd_ms": round(fb_ms, 4),
+        "stokes": stokes,
+        "kernel_stacks": stacks,
+        "differentiable": diff,
         "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def bench_stacks(mwagrid, synth, stream, steps):
+    """Kernel stacks (128 antennas x 8 channels x 16 times, 4096^2 grid, O = 4, A-term x
+    w-plane kernels of support 21...45): grid and degrid times. This workload is bound by
+    LDS and VALU work on the taps, not by HBM: it is reported against the FP32 vector peak
+    with 8 flop per tap (a complex tap times a complex visibility, added: 4 FMAs)."""
+    import numpy as np
+    import torch
+    wl = synth.beam_w_stacks()
+    spec = mwagrid.InstanceSpec.from_workload(wl, with_ants=False)
+    t0 = time.perf_counter()
+    plan = mwagrid.Plan(spec)
+    torch.cuda.synchronize()
+    pms = (time.perf_counter() - t0) * 1e3
+    vis = torch.from_numpy(wl.vis).cuda()
+    grid = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device="cuda")
+    vout = torch.empty_like(vis)
+    plan.grid(vis, out=grid)
+    plan.degrid(grid, out=vout)
+    g = percentiles(lambda: plan.grid(vis, out=grid), steps, stream)
+    d = percentiles(lambda: plan.degrid(grid, out=vout), steps, stream)
+    info = plan.info(0)
+    plan.close()
+    sup = wl.kernel_support[wl.kernel_index[wl.flags == 0]].astype(np.int64)
+    taps = int((sup * sup).sum())
+    flop = 8 * taps  # complex x complex multiply-add per tap
+    out = {"workload": "beam_w_stacks: 128 antennas x 8 ch x 16 times, 4096^2, O=4, supports 21..45",
+           "visibilities": int(info["nkept"]), "taps": taps, "plan_ms": round(pms, 1),
+           "grid_ms": g, "degrid_ms": d,
+           "grid_mvis_s": round(info["nkept"] / (g["median"] * 1e-3) / 1e6, 1),
+           "grid_tflops": round(flop / (g["median"] * 1e-3) / 1e12, 2),
+           "grid_frac_fp32_vector": round(flop / (g["median"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
+           "launch": {k: info[k] for k in ("tile", "variant", "wg_waves", "nwork")}}
+    log(f"kernel stacks: {out}")
+    return out
+
+
+def bench_differentiable(mwagrid, synth, stream, steps):
+    """Differentiable imaging (128 antennas x 8 ch x 4 times, 1024^2): forward = gains ->
+    grid -> image, loss = ||image - target||^2, backward through the hand-written adjoints to
+    the visibilities and gains, as one autograd step."""
+    import numpy as np
+    import torch
+    from paper_0902_0915_amd.mwagrid import grid_image
+    wl = synth.differentiable()
+    spec = mwagrid.InstanceSpec.from_workload(wl)
+    plan = mwagrid.Plan(spec)
+    vis = torch.from_numpy(wl.vis).cuda().requires_grad_(True)
+    g = torch.from_numpy(wl.gains.astype(np.complex64)).cuda().requires_grad_(True)
+    with torch.no_grad():
+        target = grid_image(vis.detach(), None, plan, correct=False).clone()
+
+    def step():
+        vis.grad = None
+        g.grad = None
+        img = grid_image(vis, g, plan, correct=False)
+        loss = torch.sum(torch.abs(img - target) ** 2)
+        loss.backward()
+
+    for _ in range(3):
+        step()
+    pct = percentiles(step, steps, stream)
+    plan.close()
+    out = {"workload": "differentiable: 128 antennas x 8 ch x 4 times, 1024^2, gains",
+           "visibilities": wl.ngroups, "fwd_bwd_ms": pct,
+           "steps_per_s": round(1e3 / pct["median"], 1)}
+    log(f"differentiable: {out}")
+    return out
 
 
 def bench_batched(mwagrid, synth, stream, steps):
@@ -285,6 +407,17 @@ def bench_batched(mwagrid, synth, stream, steps):
             "batched_plan_ms": round(bplan_ms, 1)}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, vis_dev, sample_groups):
     """The FP64 oracle (as it stands) on the same workload, or its first ``sample_groups``
     groups: positions, gridding (all host cores, row stripes) and the image with
@@ -311,12 +444,31 @@ def cpu_baseline(wl, vis_dev, sample_groups):
     dt = total / passes
     nv = int(keep.sum()) * wl.npol
     log(f"cpu baseline: {passes} passes, {dt:.2f} s each")
+    # one core, on the first sixteenth of the rows (the same per-visibility work)
+    nrow1 = max(1, nrow // 16)
+    ng1 = nrow1 * wl.nchan
+    vis1 = vis[:ng1]
+    t1, p1 = 0.0, 0
+    while p1 < 4 and (p1 == 0 or t1 < 8.0):
+        t0 = time.perf_counter()
+        pos, keep1, _ = orc.positions(wl.uvw[:nrow1], wl.freq, wl.nx, wl.ny, wl.du, wl.dv, wl.W, wl.O)
+        G = orc.grid(pos, keep1, vis1, wl.nx, wl.ny, wl.W, wl.O, nchan=wl.nchan, nthreads=1)
+        orc.image(G, W=wl.W, correct=True)
+        t1 += time.perf_counter() - t0
+        p1 += 1
+    nv1 = int(keep1.sum()) * wl.npol
+    log(f"cpu baseline, one core: {p1} passes, {t1 / p1:.2f} s each")
     return {"value": round(nv / dt / 1e6, 3), "unit": "Mvis/s", "cores": cores,
-            "kind": "oracle", "seconds": round(total, 2), "passes": passes,
+            "kind": "oracle", "seconds": round(total, 2), "passes": passes, "cpu_model": cpu_model(),
             "sample": (f"the whole workload ({nv} kept visibilities)" if nrow == wl.uvw.shape[0] else
                        f"first {nrow} rows x {wl.nchan} channels x {wl.npol} pols of the same "
                        f"workload ({nv} visibilities)")
-                      + f", positions + grid + corrected image, mean of {passes} passes"}
+                      + f", positions + grid + corrected image, mean of {passes} passes",
+            "single_core": {"value": round(nv1 / (t1 / p1) / 1e6, 3), "unit": "Mvis/s", "cores": 1,
+                            "seconds": round(t1, 2), "passes": p1,
+                            "sample": f"first {nrow1} rows x {wl.nchan} channels x {wl.npol} pols "
+                                      f"({nv1} visibilities), positions + grid + corrected image "
+                                      "(the 2048^2 image transform included in each pass)"}}
 
 
 if __name__ == "__main__":

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MW_ABI_VERSION 3
+#define MW_ABI_VERSION 4
 
 typedef enum {
     MW_OK = 0,
@@ -104,7 +104,13 @@ typedef struct {
                            5 = kernel stacks, gathered by output tile (chosen for stacks) */
     int32_t flush;      /* 1 = atomic adds of each finished tile into the zeroed grid,
                            2 = tiles to a scratch buffer, then a merge pass writes the grid
-                           (with variant 4 the result is then bit-reproducible) */
+                           (with variant 4 the result is then bit-reproducible),
+                           3 = owner tiles (variant 4, schedule 1, tile >= W - 1): each
+                           output tile is gridded by one wavefront from every group whose
+                           footprint reaches it and written once, no scratch, no merge
+                           (bit-reproducible; for sparse instances). A multi-instance plan
+                           takes 3 by itself for instances with at most 4096 such groups
+                           per output tile */
     int32_t autotune;   /* 1 = time candidate launches (tile, waves, split, schedule; the
                            default launch first) on this plan's own positions and keep the
                            fastest. Non-zero fields above stay fixed; flush stays 2 (the
@@ -153,7 +159,7 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst,
  * vis[i]: device complex64 [ngroups][npol]. gains: NULL, or gains[i] NULL or device
  * complex64 [nant]. grid[i]: device complex64 [npol][ny][nx]. accumulate = 0 overwrites the
  * grid (zeroing is part of the call); 1 adds to it. FP32 accumulation; the summation order
- * is fixed (bit-reproducible results) only with variant 4 and flush 2.
+ * is fixed (bit-reproducible results) only with variant 4 and flush 2 or 3.
  * Errors: MW_ERR_INVALID_ARG (null plan/arrays), MW_ERR_STATE (gains for an instance planned
  * without antennas), MW_ERR_HIP (launch failure).
  */
@@ -188,6 +194,25 @@ mw_status mw_degrid(mw_plan plan, const void *const *grid, const void *const *ga
  */
 mw_status mw_image(mw_plan plan, const void *const *in, void *const *out, int32_t direction,
                    int32_t correct, void *stream);
+
+/*
+ * Stokes conversion, per instance (Section 2.1: the instrumental-polarisation images are
+ * converted to Stokes parameters by a 4 x 4 matrix that depends on time and on the pixel's
+ * position relative to the instrument, at every pixel; Table 1 "Stokes Conversion").
+ * images[i]: device complex64 [4][ny][nx], the XX, XY, YX, YY images as mw_image returns
+ * them from visibilities gridded without their Hermitian mirror; the pixel's measured
+ * coherency is then E = [[2 Re XX, XY + conj(YX)], [YX + conj(XY), 2 Re YY]].
+ * jones: NULL, or jones[i] NULL (ideal feeds, J = 1) or device complex64 [ny][nx][2][2], the
+ * instrument's response J toward each pixel for the snapshot's time, row-major
+ * (J00, J01, J10, J11), with measured = J C J^H. The sky coherency C = J^-1 E J^-H gives
+ * out[i]: device float32 [4][ny][nx] = I = (C00 + C11)/2, Q = (C00 - C11)/2, U = Re C01,
+ * V = Im C01 (overwritten). A singular J gives non-finite values at its pixel (no error).
+ * images and jones must be 16-byte aligned, out 8-byte aligned. FP32 arithmetic.
+ * Errors: MW_ERR_INVALID_ARG (null arrays, misalignment), MW_ERR_STATE (an instance without
+ * 4 polarisations), MW_ERR_HIP.
+ */
+mw_status mw_stokes(mw_plan plan, const void *const *images, const void *const *jones,
+                    void *const *out, void *stream);
 
 /* Statistics and chosen launch of instance inst (inst = -1: sums over instances). */
 mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out);

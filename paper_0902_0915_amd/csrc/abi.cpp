@@ -75,7 +75,7 @@ mwg::Status validate_tuning(const mw_tuning &t) {
         return make_error(MW_ERR_INVALID_ARG, "tuning.wg_waves must be 0, 1, 2, 4, 8 or 16");
     if (t.order < 0 || t.order > 3) return make_error(MW_ERR_INVALID_ARG, "tuning.order must be 0 ... 3");
     if (t.variant < 0 || t.variant > 5) return make_error(MW_ERR_INVALID_ARG, "tuning.variant must be 0..5");
-    if (t.flush < 0 || t.flush > 2) return make_error(MW_ERR_INVALID_ARG, "tuning.flush must be 0, 1 or 2");
+    if (t.flush < 0 || t.flush > 3) return make_error(MW_ERR_INVALID_ARG, "tuning.flush must be 0 ... 3");
     if (t.schedule < 0 || t.schedule > 3) return make_error(MW_ERR_INVALID_ARG, "tuning.schedule must be 0 ... 3");
     return mwg::Status::Ok();
 }
@@ -265,6 +265,29 @@ mw_status mw_image(mw_plan plan, const void *const *in, void *const *out, int32_
         return ok();
     } catch (...) {
         return fail(MW_ERR_HIP, "unexpected exception in mw_image");
+    }
+}
+
+mw_status mw_stokes(mw_plan plan, const void *const *images, const void *const *jones, void *const *out,
+                    void *stream) {
+    try {
+        mwg::Status s = check_plan(plan);
+        if (!s.ok()) return fail(s);
+        if (!images || !out) return fail(MW_ERR_INVALID_ARG, "images and out arrays are required");
+        mwg::Plan *P = (mwg::Plan *)plan;
+        for (size_t i = 0; i < P->inst.size(); i++) {
+            if (!images[i] || !out[i]) return fail(MW_ERR_INVALID_ARG, "images[i] and out[i] must be device pointers");
+            if (P->inst[i]->npol != 4) return fail(MW_ERR_STATE, "Stokes conversion needs 4 polarisations");
+        }
+        for (size_t i = 0; i < P->inst.size(); i++) {
+            s = mwg::launch_stokes(*P->inst[i], (const float2 *)images[i],
+                                   jones ? (const float2 *)jones[i] : nullptr, (float *)out[i],
+                                   (hipStream_t)stream);
+            if (!s.ok()) return fail(s);
+        }
+        return ok();
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_stokes");
     }
 }
 

@@ -24,10 +24,15 @@
 namespace mwg {
 
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
+size_t owner_lds(int npol, int T, int W, int O, int waves);
 Status launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 Status ensure_partial(Instance &I, hipStream_t s);
 
 namespace {
+
+// Most groups an output tile may receive for an instance of a batch to take the owner-tile
+// flush (one wave grids the whole list).
+constexpr int64_t kOwnerCap = 4096;
 
 struct BatchDesc {
     // refreshed per call
@@ -42,14 +47,30 @@ struct BatchDesc {
     const int32_t *tile_work, *work_ids;
     const int32_t *mblocks; // merge blocks some work item reaches, then those none reaches
     int32_t nx, ny, ntx, nty, nwork, nant, ndropped, n_mblocks;
+    // flush 3 (owner tiles): the instance's work items are output tiles over its pair lists
+    int32_t flush;
+    int32_t item0;  // index of the instance's first gridder record in the batch
+    const WorkItem *owork;
+    const uint32_t *pperm, *pcode, *psant;
+    const float *psw;
 };
 
 struct BatchItem {
     int32_t inst, item;
 };
 
+// One gridder work item of the batch, self-contained so that a wave needs one record load
+// before it can start on the item's groups: the instance, the tile (index in the instance's
+// tile grid), the group range and the arrays it indexes (sorted or per-pair).
+struct GridItem {
+    int32_t inst, tile, begin, end;
+    const uint32_t *perm, *code;
+};
+
 struct Batch {
     int ninst = 0, npol = 1, W = 7, O = 8, T = 8, waves = 8, STR = 0, PL = 0, nitems = 0;
+    int STR3 = 0, PL3 = 0, per_wave = 0;  // flush-3 LDS tile; LDS floats per wave (either form)
+    int64_t ztiles = 0;                   // output tiles of flush-3 instances written as zeros
     int dthreads = 256;  // threads per degridder workgroup
     int grid_blocks = 0;     // gridder workgroups (waves of them, one work item per wave)
     int64_t merge_blocks = 0, zero_blocks = 0, prologue_n = 0;
@@ -59,9 +80,14 @@ struct Batch {
     BatchDesc *d_desc = nullptr, *h_desc = nullptr; // h_desc: pinned host memory
     hipEvent_t desc_ev = nullptr;
     bool desc_pending = false;
-    BatchItem *d_items = nullptr;
+    GridItem *d_items = nullptr;    // gridder items (owner tiles for flush-3 instances)
+    hipStream_t side = nullptr;     // second branch of the gridding sequence (zero fills)
+    hipEvent_t fork = nullptr, join = nullptr;
+    BatchItem *d_ditems = nullptr;  // degridder items (every instance's source-tile items)
+    int nditems = 0;
     int64_t *d_pro_start = nullptr;
     int2 *d_mpairs = nullptr; // (instance, block) of every merge block, then of every zero block
+    int2 *d_ztiles = nullptr; // (instance, output tile) of every zero tile of flush-3 instances
     const float *tab8 = nullptr;
     float tapk[16 * 8] = {0};
     hipStream_t cap = nullptr;
@@ -71,9 +97,9 @@ struct Batch {
 
 struct BatchGridArgs {
     const BatchDesc *desc;
-    const BatchItem *items;
+    const GridItem *items;
     const float *tab8;
-    int nitems, O, T, STR, PL;
+    int nitems, O, T, STR, PL, STR3, PL3, per_wave;
     float tapk[16 * 8];
 };
 
@@ -103,37 +129,41 @@ __global__ __launch_bounds__(1024) void k_grid_batched(BatchGridArgs a) {
     const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
     if (w >= a.nitems) return;
     const int R = a.T + W - 1;
-    float *stage = smem + ntab + wave * wavetile_per_wave(NC, a.PL);
-    const BatchItem it = a.items[w];
-    const int inst = uni(it.inst), item = uni(it.item);
+    float *stage = smem + ntab + wave * a.per_wave;
+    const GridItem it = a.items[w];
+    const int inst = uni(it.inst), wtile = uni(it.tile);
     const BatchDesc &d = a.desc[inst];
-    const WorkItem wk = d.work[item];
-    const int ntx = uni(d.ntx), wtile = uni(wk.tile);
+    const bool owner = uni(d.flush) == 3;
+    const int ntx = uni(d.ntx);
+    const int PL = owner ? a.PL3 : a.PL;
     float *tile = stage + kStageFloats;
-    for (int i = lane; i < NC * a.PL; i += 64) tile[i] = 0.0f;
+    for (int i = 4 * lane; i < NC * PL; i += 256) *(float4 *)(tile + i) = make_float4(0.f, 0.f, 0.f, 0.f);
     ItemCtx c;
     c.tile = tile;
     c.sv = stage;
     c.vis = uni(d.vis);
     c.gains = uni(d.gains);
-    c.perm = uni(d.perm);
-    c.scode = uni(d.scode);
-    c.sant = uni(d.sant);
-    c.sw = uni(d.sw);
+    c.perm = uni(it.perm);
+    c.scode = uni(it.code);
+    c.sant = uni(owner ? d.psant : d.sant);
+    c.sw = uni(owner ? d.psw : d.sw);
     c.tapk = a.tapk;
     c.ltab = ltab;
     c.grid = uni(d.grid);
-    c.partial = uni(d.partial) + (int64_t)item * NC * R * R;
-    c.wb = uni(wk.begin);
-    c.we = uni(wk.end);
+    // flush 2: the item's partial slice (items of an instance are numbered by its work list,
+    // the record's position within the instance's contiguous run of records)
+    c.partial = owner ? nullptr : uni(d.partial) + (int64_t)(w - uni(d.item0)) * NC * R * R;
+    c.wb = uni(it.begin);
+    c.we = uni(it.end);
     c.tx0 = (wtile % ntx) * a.T;
     c.ty0 = (wtile / ntx) * a.T;
     c.T = a.T;
-    c.STR = a.STR;
-    c.PL = a.PL;
+    c.STR = owner ? a.STR3 : a.STR;
+    c.PL = PL;
     c.nx = uni(d.nx);
     c.ny = uni(d.ny);
-    c.flush = 2;
+    c.flush = owner ? 3 : 2;
+    c.accumulate = uni(d.accumulate);
     wavetile_item<NPOL, W>(c, lane);
 }
 
@@ -176,6 +206,21 @@ __global__ __launch_bounds__(kMergeB * kMergeB) void k_zero_batched(const BatchD
     const int bpr = (d.nx + kMergeB - 1) / kMergeB;
     const int by = pr.y / bpr, bx = pr.y - by * bpr;
     zero_block<NPOL>(d.grid, d.nx, d.ny, bx * kMergeB, by * kMergeB);
+}
+
+// Zeros of the output tiles of flush-3 instances that no footprint reaches (nothing when
+// accumulating), one tile per wave.
+template <int NPOL>
+__global__ __launch_bounds__(256) void k_zero_tiles_batched(const BatchDesc *desc, const int2 *pairs, int64_t n,
+                                                            int T) {
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t k = (int64_t)blockIdx.x * 4 + wave; k < n; k += nw) {
+        const int2 pr = pairs[k];
+        const BatchDesc &d = desc[pr.x];
+        if (d.accumulate) continue;
+        zero_tile<NPOL>(d.grid, d.nx, d.ny, (pr.y % d.ntx) * T, (pr.y / d.ntx) * T, T, lane, 64);
+    }
 }
 
 // Zeroes the adjoint outputs of dropped groups (entries [0, start[ninst]) of the dropped
@@ -244,7 +289,30 @@ Status enqueue_grid(Batch &B, hipStream_t s) {
     a.T = B.T;
     a.STR = B.STR;
     a.PL = B.PL;
+    a.STR3 = B.STR3;
+    a.PL3 = B.PL3;
+    a.per_wave = B.per_wave;
     std::memcpy(a.tapk, B.tapk, sizeof a.tapk);
+    // The zero fills write cells no work item reaches, disjoint from everything the gridder
+    // and the merge write: they run on a second branch (a parallel branch of the captured
+    // graph), so the bandwidth-bound fill overlaps the latency-bound gridder.
+    const bool fork = B.zero_blocks > 0 || B.ztiles > 0;
+    if (fork) {
+        MWG_HIP(hipEventRecord(B.fork, s));
+        MWG_HIP(hipStreamWaitEvent(B.side, B.fork, 0));
+        if (B.zero_blocks > 0) {
+            hipLaunchKernelGGL(k_zero_batched<NPOL>, dim3((unsigned)B.zero_blocks), dim3(kMergeB * kMergeB), 0,
+                               B.side, B.d_desc, (const int2 *)B.d_mpairs + B.merge_blocks);
+            MWG_HIP(hipGetLastError());
+        }
+        if (B.ztiles > 0) {
+            const int64_t wg = std::min<int64_t>((B.ztiles + 3) / 4, 4096);
+            hipLaunchKernelGGL(k_zero_tiles_batched<NPOL>, dim3((unsigned)wg), dim3(256), 0, B.side, B.d_desc,
+                               (const int2 *)B.d_ztiles, B.ztiles, B.T);
+            MWG_HIP(hipGetLastError());
+        }
+        MWG_HIP(hipEventRecord(B.join, B.side));
+    }
     const dim3 g(B.grid_blocks), b(64 * B.waves);
     switch (B.W) {
     case 3: hipLaunchKernelGGL((k_grid_batched<NPOL, 3>), g, b, B.grid_lds, s, a); break;
@@ -258,11 +326,7 @@ Status enqueue_grid(Batch &B, hipStream_t s) {
                            B.d_desc, (const int2 *)B.d_mpairs, ilog2(B.T), B.W);
         MWG_HIP(hipGetLastError());
     }
-    if (B.zero_blocks > 0) {
-        hipLaunchKernelGGL(k_zero_batched<NPOL>, dim3((unsigned)B.zero_blocks), dim3(kMergeB * kMergeB), 0, s,
-                           B.d_desc, (const int2 *)B.d_mpairs + B.merge_blocks);
-        MWG_HIP(hipGetLastError());
-    }
+    if (fork) MWG_HIP(hipStreamWaitEvent(s, B.join, 0));
     return Status::Ok();
 }
 
@@ -273,9 +337,9 @@ Status enqueue_degrid(Batch &B, int64_t ndrop_total, hipStream_t s) {
                            s, B.d_desc, (const int64_t *)B.d_pro_start, B.ninst, ndrop_total);
         MWG_HIP(hipGetLastError());
     }
-    if (B.nitems > 0) {
-        hipLaunchKernelGGL(k_degrid_batched<NPOL>, dim3(B.nitems), dim3(B.dthreads), B.degrid_lds, s, B.d_desc,
-                           B.d_items, B.T, B.W, B.O, B.ant_in_lds);
+    if (B.nditems > 0) {
+        hipLaunchKernelGGL(k_degrid_batched<NPOL>, dim3(B.nditems), dim3(B.dthreads), B.degrid_lds, s, B.d_desc,
+                           B.d_ditems, B.T, B.W, B.O, B.ant_in_lds);
         MWG_HIP(hipGetLastError());
     }
     return Status::Ok();
@@ -371,8 +435,19 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     const Instance &I0 = *P.inst[0];
     for (const Instance *I : P.inst) {
         if (I->stacks || I->npol != I0.npol || I->W != I0.W || I->O != I0.O || I->L.variant != 4 ||
-            I->L.flush != 2 || I->L.tile != I0.L.tile || I->L.wg_waves != I0.L.wg_waves)
+            (I->L.flush != 2 && I->L.flush != 3) || I->L.schedule != 1 || I->L.tile != I0.L.tile ||
+            I->L.wg_waves != I0.L.wg_waves)
             return Status::Ok();
+    }
+    // Instances whose output tiles each receive at most kOwnerCap groups take the owner-tile
+    // flush: every cell written once, no scratch tiles, no merge. Denser ones keep the merge.
+    for (Instance *I : P.inst) {
+        if (I->L.flush != 2 || I->flush_fixed || I->L.tile < I->W - 1 ||
+            owner_lds(I->npol, I->L.tile, I->W, I->O, I->L.wg_waves) > 160 * 1024)
+            continue;
+        bool built = false;
+        MWG_TRY(build_owner_schedule(*I, kOwnerCap, &built, s));
+        if (built) I->L.flush = 3;
     }
     Batch *B = new Batch();
     P.batch = B;
@@ -385,6 +460,14 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     const int R = B->T + B->W - 1;
     B->STR = R;
     B->PL = plane2(R, R, B->W);
+    B->STR3 = owner_span(B->T, B->W);
+    B->PL3 = owner_plane(B->T, B->W);
+    {
+        bool any3 = false;
+        for (const Instance *I : P.inst) any3 = any3 || I->L.flush == 3;
+        B->per_wave = std::max(wavetile_per_wave(2 * B->npol, B->PL),
+                               any3 ? wavetile_per_wave(2 * B->npol, B->PL3) : 0);
+    }
     B->tab8 = I0.tab8;
     for (int r = 0; r < I0.O; r++)
         for (int t = 0; t < I0.W; t++) B->tapk[r * 8 + t] = I0.h_tab[(size_t)r * I0.W + t];
@@ -392,12 +475,14 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     B->use_graph = !(ng && ng[0] == '1');
     // descriptors (fixed part)
     std::vector<BatchDesc> desc(B->ninst);
-    std::vector<BatchItem> items;
-    std::vector<int64_t> mstart(B->ninst + 1, 0), zstart(B->ninst + 1, 0), pstart(2 * B->ninst + 1, 0);
+    std::vector<GridItem> items;
+    std::vector<BatchItem> ditems;
+    std::vector<int64_t> pstart(2 * B->ninst + 1, 0);
     int max_nant = 0;
     for (int i = 0; i < B->ninst; i++) {
         Instance &I = *P.inst[i];
-        MWG_TRY(ensure_partial(I, s));
+        const bool owner = I.L.flush == 3;
+        if (!owner) MWG_TRY(ensure_partial(I, s));
         BatchDesc &d = desc[i];
         std::memset(&d, 0, sizeof d);
         d.perm = I.perm;
@@ -420,10 +505,25 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         d.nwork = I.nwork;
         d.nant = I.nant;
         d.ndropped = (int)(I.ngroups - I.nkept);
+        d.flush = I.L.flush;
+        if (owner) {
+            d.owork = I.owork;
+            d.pperm = I.pperm;
+            d.pcode = I.pcode;
+            d.psant = I.psant;
+            d.psw = I.psw;
+        }
         max_nant = std::max(max_nant, I.nant);
-        for (int w = 0; w < I.nwork; w++) items.push_back({i, w});
-        mstart[i + 1] = mstart[i] + I.n_mblocks;
-        zstart[i + 1] = zstart[i] + I.n_zblocks;
+        {
+            const int nw = owner ? I.nowork : I.nwork;
+            std::vector<WorkItem> wl((size_t)nw);
+            if (nw > 0)
+                MWG_HIP(hipMemcpy(wl.data(), owner ? I.owork : I.work, sizeof(WorkItem) * nw, hipMemcpyDeviceToHost));
+            d.item0 = (int32_t)items.size();
+            for (const WorkItem &wk : wl)
+                items.push_back({i, wk.tile, wk.begin, wk.end, owner ? I.pperm : I.perm, owner ? I.pcode : I.scode});
+        }
+        for (int w = 0; w < I.nwork; w++) ditems.push_back({i, w});
         pstart[i + 1] = pstart[i] + d.ndropped;
     }
     // second half: gain-gradient entries, numbered after all dropped entries
@@ -434,13 +534,12 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     // time, which stay in cache. Interleaving all instances largest-first spreads the random
     // gathers over every instance at once and runs ~4x slower.
     B->nitems = (int)items.size();
+    B->nditems = (int)ditems.size();
     {
         int64_t kept = 0;
         for (Instance *I : P.inst) kept += I->nkept;
-        B->dthreads = degrid_threads(kept, B->nitems);
+        B->dthreads = degrid_threads(kept, B->nditems);
     }
-    B->merge_blocks = mstart[B->ninst];
-    B->zero_blocks = zstart[B->ninst];
     void *p;
     MWG_TRY(B->arena.alloc(&p, sizeof(BatchDesc) * B->ninst));
     B->d_desc = (BatchDesc *)p;
@@ -450,36 +549,57 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     }
     std::memcpy(B->h_desc, desc.data(), sizeof(BatchDesc) * B->ninst);
     MWG_HIP(hipMemcpy(B->d_desc, desc.data(), sizeof(BatchDesc) * B->ninst, hipMemcpyHostToDevice));
-    MWG_TRY(B->arena.alloc(&p, sizeof(BatchItem) * std::max<size_t>(items.size(), 1)));
-    B->d_items = (BatchItem *)p;
+    MWG_TRY(B->arena.alloc(&p, sizeof(GridItem) * std::max<size_t>(items.size(), 1)));
+    B->d_items = (GridItem *)p;
     if (!items.empty())
-        MWG_HIP(hipMemcpy(B->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice));
+        MWG_HIP(hipMemcpy(B->d_items, items.data(), sizeof(GridItem) * items.size(), hipMemcpyHostToDevice));
+    MWG_TRY(B->arena.alloc(&p, sizeof(BatchItem) * std::max<size_t>(ditems.size(), 1)));
+    B->d_ditems = (BatchItem *)p;
+    if (!ditems.empty())
+        MWG_HIP(hipMemcpy(B->d_ditems, ditems.data(), sizeof(BatchItem) * ditems.size(), hipMemcpyHostToDevice));
     {
-        // (instance, block) pairs: all merge blocks, then all zero blocks
-        std::vector<int2> mp;
-        mp.reserve((size_t)(B->merge_blocks + B->zero_blocks));
+        // (instance, block) pairs of flush-2 instances: all merge blocks, then all zero
+        // blocks; (instance, tile) pairs of the zero tiles of flush-3 instances
+        std::vector<int2> mp, zt;
         std::vector<std::vector<int32_t>> lists(B->ninst);
         for (int i = 0; i < B->ninst; i++) {
             const Instance &I = *P.inst[i];
+            if (I.L.flush == 3) {
+                std::vector<int32_t> z((size_t)I.n_ozero);
+                if (!z.empty()) MWG_HIP(hipMemcpy(z.data(), I.ozero, 4 * z.size(), hipMemcpyDeviceToHost));
+                for (int32_t t : z) zt.push_back(make_int2(i, t));
+                continue;
+            }
             lists[i].resize((size_t)(I.n_mblocks + I.n_zblocks));
             if (!lists[i].empty())
                 MWG_HIP(hipMemcpy(lists[i].data(), I.mblocks, 4 * lists[i].size(), hipMemcpyDeviceToHost));
             for (int k = 0; k < I.n_mblocks; k++) mp.push_back(make_int2(i, lists[i][k]));
         }
+        B->merge_blocks = (int64_t)mp.size();
         for (int i = 0; i < B->ninst; i++)
-            for (int k = P.inst[i]->n_mblocks; k < (int)lists[i].size(); k++) mp.push_back(make_int2(i, lists[i][k]));
+            if (P.inst[i]->L.flush != 3)
+                for (int k = P.inst[i]->n_mblocks; k < (int)lists[i].size(); k++) mp.push_back(make_int2(i, lists[i][k]));
+        B->zero_blocks = (int64_t)mp.size() - B->merge_blocks;
+        B->ztiles = (int64_t)zt.size();
         MWG_TRY(B->arena.alloc(&p, sizeof(int2) * std::max<size_t>(mp.size(), 1)));
         B->d_mpairs = (int2 *)p;
         if (!mp.empty())
             MWG_HIP(hipMemcpy(B->d_mpairs, mp.data(), sizeof(int2) * mp.size(), hipMemcpyHostToDevice));
+        MWG_TRY(B->arena.alloc(&p, sizeof(int2) * std::max<size_t>(zt.size(), 1)));
+        B->d_ztiles = (int2 *)p;
+        if (!zt.empty())
+            MWG_HIP(hipMemcpy(B->d_ztiles, zt.data(), sizeof(int2) * zt.size(), hipMemcpyHostToDevice));
     }
     MWG_TRY(B->arena.alloc(&p, sizeof(int64_t) * pstart.size()));
     B->d_pro_start = (int64_t *)p;
     MWG_HIP(hipMemcpy(B->d_pro_start, pstart.data(), sizeof(int64_t) * pstart.size(), hipMemcpyHostToDevice));
     MWG_HIP(hipEventCreateWithFlags(&B->desc_ev, hipEventDisableTiming));
     MWG_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    MWG_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    MWG_HIP(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+    MWG_HIP(hipEventCreateWithFlags(&B->join, hipEventDisableTiming));
     // launch shapes
-    B->grid_lds = wavetiles_lds(B->npol, B->T, B->W, B->O, B->waves);
+    B->grid_lds = 4 * ((size_t)B->O * 8 + (size_t)B->waves * B->per_wave);
     B->grid_blocks = std::max(1, (B->nitems + B->waves - 1) / B->waves);
     const int Rd = B->T + B->W - 1;
     B->degrid_lds = sizeof(float2) * (size_t)B->npol * Rd * Rd + 4 * (size_t)((B->O * B->W + 1) & ~1);
@@ -513,6 +633,9 @@ void batch_release(Plan &P) {
     if (B->x_degrid) (void)hipGraphExecDestroy(B->x_degrid);
     if (B->desc_ev) (void)hipEventDestroy(B->desc_ev);
     if (B->cap) (void)hipStreamDestroy(B->cap);
+    if (B->side) (void)hipStreamDestroy(B->side);
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    if (B->join) (void)hipEventDestroy(B->join);
     if (B->h_desc) (void)hipHostFree(B->h_desc);
     B->arena.release();
     delete B;

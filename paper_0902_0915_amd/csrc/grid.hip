@@ -29,6 +29,7 @@ namespace mwg {
 size_t taplanes_lds(int npol, int T, int W, int O, int waves);
 size_t collanes_lds(int npol, int T, int W, int O, int waves);
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
+size_t owner_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
 Status ensure_partial(Instance &I, hipStream_t s);
 
@@ -64,6 +65,7 @@ struct GridArgs {
     int xcd_start[9];
     int schedule;
     const int2 *coop;  // schedule 3: wave slots
+    int accumulate;    // flush 3: add the output tiles to the grid
 };
 
 // LDS layout of a tile: 2*NPOL planes (re, im of each polarisation), each R rows of STR
@@ -413,7 +415,8 @@ __global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, 
     c.tapk = a.tapk;
     c.ltab = ltab;
     c.grid = a.grid;
-    c.partial = a.partial + (int64_t)widx * NC * R * R;
+    c.partial = flush == 2 ? a.partial + (int64_t)widx * NC * R * R : nullptr;
+    c.accumulate = a.accumulate;
     c.wb = wk.begin;
     c.we = wk.end;
     c.tx0 = (wk.tile % a.ntx) * a.T;
@@ -583,10 +586,25 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
     const int flush = L.flush;
     if (flush == 2) MWG_TRY(ensure_partial(I, s));
     a.partial = I.partial;
+    int nwork = I.nwork;
+    if (flush == 3) {
+        // owner tiles: the work list, codes and sorted arrays of the (output tile, group) pairs
+        if (L.variant != 4 || I.owner_tile != L.tile)
+            return make_error(MW_ERR_STATE, "flush 3 needs the owner-tile schedule of the wave-tile gridder");
+        a.work = I.owork;
+        a.perm = I.pperm;
+        a.scode = I.pcode;
+        a.sw = I.psw;
+        a.sant = I.psant;
+        a.str = owner_span(L.tile, I.W);
+        a.plane = owner_plane(L.tile, I.W);
+        a.accumulate = accumulate;
+        nwork = I.nowork;
+    }
     if (flush == 1 && !accumulate)
         MWG_TRY(launch_fill_zero(a.grid, sizeof(float2) * (size_t)NPOL * I.nx * I.ny, s));
     if (I.timing) MWG_HIP(hipEventRecord(I.tev[0], s));
-    if (I.nwork > 0) {
+    if (nwork > 0) {
         if (L.variant == 1) {
             const size_t lds = taplanes_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
@@ -602,7 +620,8 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
             default: return make_error(MW_ERR_UNSUPPORTED, "variant 2 needs W in {3, 5, 7}");
             }
         } else if (L.variant == 4) {
-            const size_t lds = wavetiles_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
+            const size_t lds = flush == 3 ? owner_lds(NPOL, L.tile, I.W, I.O, L.wg_waves)
+                                          : wavetiles_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
             if (L.schedule == 3) {
                 a.coop = I.coop;
@@ -614,14 +633,14 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
                 default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
                 }
             } else {
-                const dim3 g(L.schedule == 2 ? 8 * I.xcd_wgs : (I.nwork + L.wg_waves - 1) / L.wg_waves),
+                const dim3 g(L.schedule == 2 ? 8 * I.xcd_wgs : (nwork + L.wg_waves - 1) / L.wg_waves),
                     b(64 * L.wg_waves);
                 a.schedule = L.schedule;
                 for (int x = 0; x < 9; x++) a.xcd_start[x] = I.xcd_start[x];
                 switch (I.W) {
-                case 3: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 3>), g, b, lds, s, a, flush, I.nwork); break;
-                case 5: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 5>), g, b, lds, s, a, flush, I.nwork); break;
-                case 7: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 7>), g, b, lds, s, a, flush, I.nwork); break;
+                case 3: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 3>), g, b, lds, s, a, flush, nwork); break;
+                case 5: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 5>), g, b, lds, s, a, flush, nwork); break;
+                case 7: hipLaunchKernelGGL((k_grid_wavetiles<NPOL, 7>), g, b, lds, s, a, flush, nwork); break;
                 default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
                 }
             }
@@ -633,6 +652,7 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
         MWG_HIP(hipGetLastError());
     }
     if (I.timing) MWG_HIP(hipEventRecord(I.tev[1], s));
+    if (flush == 3 && !accumulate) MWG_TRY(launch_zero_tiles(I, a.grid, s));
     if (flush == 2) {
         const int nzero = accumulate ? 0 : I.n_zblocks;
         if (I.n_mblocks + nzero > 0) {
@@ -666,6 +686,10 @@ size_t collanes_lds(int npol, int T, int W, int O, int waves) {
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves) {
     const int R = T + W - 1, PL = tile_plane2(R, R, W);
     return 4 * ((size_t)O * 8 + (size_t)waves * wavetile_per_wave(2 * npol, PL));
+}
+
+size_t owner_lds(int npol, int T, int W, int O, int waves) {
+    return 4 * ((size_t)O * 8 + (size_t)waves * wavetile_per_wave(2 * npol, owner_plane(T, W)));
 }
 
 size_t scatter_lds(int npol, int T, int W, int O) {

@@ -14,10 +14,26 @@ struct ItemCtx {
     const float *tapk;   // tap rows padded to 8 floats, in constant (kernel-argument) memory
     const float *ltab;   // the same table in LDS
     float *tile, *sv;    // this wave's LDS tile (NC planes of PL floats) and staging area
-    float2 *grid;        // flush 1 target
+    float2 *grid;        // flush 1 and 3 target
     float *partial;      // flush 2 target: this work item's slice
     int wb, we, tx0, ty0, T, STR, PL, nx, ny, flush;
+    int accumulate;      // flush 3: add to the grid instead of overwriting it
 };
+
+// Flush 3 ("owner tiles"): a work item is an output tile and its list holds every group whose
+// footprint reaches the tile, from the tile itself and its neighbours. The wave's LDS tile
+// then spans the output tile with a margin of 2h cells (R3 = T + 4h rows), so that every
+// such footprint lies inside it, and only the T x T output cells are written, once, straight
+// to the grid: no partial buffer and no merge pass.
+__host__ __device__ inline int owner_span(int T, int W) { return T + 2 * (W - 1); }
+// plane size of a flush-3 tile (row stride R3), congruent to W (mod 32) like the other
+// wave tiles so that the component planes of one lane set fall in distinct banks
+__host__ __device__ inline int owner_plane(int T, int W) {
+    const int R3 = owner_span(T, W);
+    int p = R3 * R3;
+    while ((p - W) % 32 != 0) p++;
+    return p;
+}
 
 template <int NPOL>
 __device__ inline void core_fetch(const ItemCtx &c, int i, uint32_t g, float2 (&v)[NPOL]) {
@@ -267,6 +283,26 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
                 if (im != 0.0f) atomicAdd(dst + 1, im);
             }
         }
+    } else if (c.flush == 3) {
+        // the output tile's T x T cells at LDS offset (2h, 2h), each written once
+        const int T = c.T, m = 2 * h;
+        for (int idx = lane; idx < T * T; idx += 64) {
+            const int r = idx / T, col = idx - r * T;
+            const int gy = ty0 + r, gx = tx0 + col;
+            if (gy >= c.ny || gx >= c.nx) continue;
+            const int o = (r + m) * STR + col + m;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                float2 v = make_float2(tile[(2 * p) * PL + o], tile[(2 * p + 1) * PL + o]);
+                float2 *dst = c.grid + ((int64_t)p * c.ny + gy) * c.nx + gx;
+                if (c.accumulate) {
+                    const float2 old = *dst;
+                    v.x += old.x;
+                    v.y += old.y;
+                }
+                *dst = v;
+            }
+        }
     } else if (c.flush == 2) {
         // the item's slice of the partial buffer: cell-major, the NC components of a cell
         // contiguous
@@ -394,6 +430,29 @@ __device__ inline void zero_block(float2 *grid, int nx, int ny, int x0, int y0) 
     if (x >= nx || y >= ny) return;
 #pragma unroll
     for (int p = 0; p < NPOL; p++) grid[((int64_t)p * ny + y) * nx + x] = make_float2(0.f, 0.f);
+}
+
+// Zeros of one T x T output tile (origin x0, y0) in the NPOL planes of a grid, written by
+// nl lanes (lane l) with 16-byte stores where the row allows (T >= 2, x0 even).
+template <int NPOL>
+__device__ inline void zero_tile(float2 *grid, int nx, int ny, int x0, int y0, int T, int l, int nl) {
+    const int half = T / 2;  // float4 (two cells) per row position
+    const bool vec = (nx % 2) == 0 && ((uintptr_t)grid & 15u) == 0;
+    for (int idx = l; idx < T * half; idx += nl) {
+        const int r = idx / half, c2 = idx - r * half;
+        const int gy = y0 + r, gx = x0 + 2 * c2;
+        if (gy >= ny || gx >= nx) continue;
+#pragma unroll
+        for (int p = 0; p < NPOL; p++) {
+            float2 *dst = grid + ((int64_t)p * ny + gy) * nx + gx;
+            if (vec && gx + 1 < nx) {
+                *(float4 *)dst = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                dst[0] = make_float2(0.f, 0.f);
+                if (gx + 1 < nx) dst[1] = make_float2(0.f, 0.f);
+            }
+        }
+    }
 }
 
 } // namespace mwg

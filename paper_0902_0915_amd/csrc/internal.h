@@ -70,7 +70,7 @@ struct Launch {
     int wg_waves = 8;  // waves per workgroup
     int order = 1;     // 1 cell-sorted, 2 input order within tile, 3 cell-sorted along the radius
     int variant = 1;   // gridder variant
-    int flush = 1;     // 1 atomic, 2 deterministic merge
+    int flush = 1;     // 1 atomic, 2 deterministic merge, 3 owner tiles (written once, no merge)
     int schedule = 1;  // 1 largest first, 2 Z-order chunks per XCD, 3 workgroup-cooperative items
 };
 
@@ -90,6 +90,7 @@ struct Instance {
     // launch
     Launch L;
     bool tile_fixed = false;  // the caller chose the tile (or asked the autotuner)
+    bool flush_fixed = false; // the caller chose the flush
     int ntx = 0, nty = 0, ntiles_nonempty = 0, nwork = 0;
     int max_work_groups = 0;  // largest work item
     int sorted_tile = 0, sorted_order = 0;   // the (tile, order) perm is currently sorted by
@@ -124,6 +125,19 @@ struct Instance {
     int32_t *mblocks = nullptr;   // merge blocks (by * bpr + bx): those some work item reaches,
     int n_mblocks = 0;            //   then the n_zblocks that none reaches (written as zeros)
     int n_zblocks = 0;
+    // flush 3 (owner tiles): per output tile, the sorted groups whose footprint reaches it
+    int owner_tile = 0;           // tile size the owner lists were built for (0: none)
+    int nowork = 0;               // owner work items: output tiles with candidates
+    int n_ozero = 0;              // output tiles without candidates (written as zeros)
+    int max_owner_groups = 0;     // largest owner work item
+    int64_t npairs_owner = 0;
+    WorkItem *owork = nullptr;    // [nowork] {tile, begin, end} into the pair arrays, largest first
+    uint32_t *pperm = nullptr;    // [npairs] original group of each (output tile, group) pair
+    uint32_t *pcode = nullptr;    // [npairs] its code relative to the output tile's LDS tile
+    float *psw = nullptr;         // [npairs] weights (or null)
+    uint32_t *psant = nullptr;    // [npairs] antenna pairs (or null)
+    int32_t *ozero = nullptr;     // [n_ozero] output tiles without candidates
+    size_t cap_pairs = 0, cap_owork = 0, cap_ozero = 0;
     float *partial = nullptr;     // merge flush scratch: [nwork][R*R][2*npol] (cell-major)
     size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)
@@ -188,6 +202,13 @@ Status launch_fft2d(const float2 *in, float2 *out, int nx, int ny, int npol, con
 Status launch_image_scale(const float2 *in, float2 *out, int nx, int ny, int npol,
                           const float *corrx, const float *corry, int checker, int divide,
                           hipStream_t s);
+
+// owner.hip
+Status build_owner_schedule(Instance &I, int64_t cap, bool *built, hipStream_t s);
+Status launch_zero_tiles(const Instance &I, float2 *grid, hipStream_t s);
+
+// stokes.hip
+Status launch_stokes(const Instance &I, const float2 *images, const float2 *jones, float *out, hipStream_t s);
 
 // batched.cpp
 Status batch_prepare(Plan &P, hipStream_t s);

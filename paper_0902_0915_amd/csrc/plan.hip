@@ -717,12 +717,17 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         }
     }
     MWG_HIP(hipStreamSynchronize(s));
+    if (L.flush == 3) {
+        bool built = false;
+        MWG_TRY(build_owner_schedule(I, 0, &built, s));
+    }
     return Status::Ok();
 }
 
 size_t taplanes_lds(int npol, int T, int W, int O, int waves);
 size_t collanes_lds(int npol, int T, int W, int O, int waves);
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
+size_t owner_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
 
 static Launch default_launch(const Instance &I) {
@@ -772,6 +777,10 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
     if (L.schedule == 3 && (L.variant != 4 || L.flush != 2))
         return make_error(MW_ERR_UNSUPPORTED, "schedule 3 is implemented for variant 4 with flush 2 only");
     if (L.schedule < 1 || L.schedule > 3) return make_error(MW_ERR_INVALID_ARG, "schedule %d", L.schedule);
+    if (L.flush == 3 && (I.stacks || L.variant != 4 || L.schedule != 1))
+        return make_error(MW_ERR_UNSUPPORTED, "flush 3 is implemented for variant 4 with schedule 1 only");
+    if (L.flush == 3 && L.tile < I.W - 1)
+        return make_error(MW_ERR_UNSUPPORTED, "flush 3 needs tiles of at least W - 1 cells");
     if (L.wg_waves < 4 && (I.stacks || L.variant != 4))
         return make_error(MW_ERR_UNSUPPORTED, "workgroups of %d waves are implemented for variant 4 only", L.wg_waves);
     if (I.stacks) {
@@ -790,12 +799,17 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         auto lds_of = [&](const Launch &X) {
             return X.variant == 1   ? taplanes_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
                    : X.variant == 2 ? collanes_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
-                   : X.variant == 4 ? wavetiles_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
+                   : X.variant == 4 ? (X.flush == 3 ? owner_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
+                                                    : wavetiles_lds(I.npol, X.tile, I.W, I.O, X.wg_waves))
                                     : scatter_lds(I.npol, X.tile, I.W, I.O);
         };
         // private wave tiles of a large tile size may not fit: without an explicit variant,
         // fall back to the shared-tile kernel of the same lane layout
-        if (L.variant == 4 && !(t && t->variant) && L.schedule == 1 && lds_of(L) > 160 * 1024) L.variant = 2;
+        if (L.variant == 4 && L.flush != 3 && !(t && t->variant) && L.schedule == 1 && lds_of(L) > 160 * 1024)
+            L.variant = 2;
+        // owner tiles of a large tile size: fewer waves per workgroup unless the caller set them
+        if (L.variant == 4 && L.flush == 3 && !(t && t->wg_waves))
+            while (L.wg_waves > 1 && lds_of(L) > 160 * 1024) L.wg_waves /= 2;
         const size_t lds = lds_of(L);
         if (lds > 160 * 1024)
             return make_error(MW_ERR_UNSUPPORTED, "launch needs %zu B of LDS (tile %d, npol %d)", lds,
@@ -973,6 +987,7 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     Launch L;
     MWG_TRY(resolve_launch(I, tuning, &L));
     I.tile_fixed = tuning && tuning->tile != 0;
+    I.flush_fixed = tuning && tuning->flush != 0;
     MWG_TRY(rebuild_schedule(I, L, s));
     if (I.stacks) MWG_TRY(build_stack_schedule(I, L, s));
 

@@ -120,7 +120,8 @@ std::vector<mw_tuning> candidates(const Instance &I, const mw_tuning &user, bool
     };
     push(mw_tuning{});
     const bool v4 = I.W >= 3 && I.W <= 7;
-    const std::vector<int> tiles = v4 ? std::vector<int>{8, 16} : std::vector<int>{16, 32, 64};
+    const std::vector<int> tiles = v4 ? (batch ? std::vector<int>{8, 16, 32} : std::vector<int>{8, 16})
+                                      : std::vector<int>{16, 32, 64};
     const std::vector<int> waves = batch ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 16};
     const std::vector<int> splits = {0, 2048, 8192, 16384};
     for (int tile : tiles)
@@ -219,11 +220,10 @@ Status autotune_plan(Plan &P, const mw_tuning &user, hipStream_t s) {
     }
     // the untuned batch (the default launch with the batch's own tile rule) is the baseline
     MWG_TRY(batch_prepare(P, s));
-    int64_t kept = 0, cells = 0, nvis = 0;
+    int64_t kept = 0, cells = 0;
     for (const Instance *I : P.inst) {
         kept += I->nkept;
         cells += (int64_t)I->nx * I->ny;
-        nvis += I->ngroups * I->npol;
     }
     char kb[256];
     {

@@ -13,6 +13,10 @@ from dataclasses import dataclass
 
 import numpy as np
 
+# torch first: the library then binds to the HIP runtime torch has already loaded, so both
+# see the same devices, contexts and allocations.
+import torch  # noqa: E402,F401
+
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmwagrid.so")
 if not os.path.exists(_LIB_PATH):
     raise RuntimeError(f"libmwagrid.so is not built ({_LIB_PATH}); run "
@@ -58,6 +62,7 @@ _lib.mw_grid_plan.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(MwInstance), _
 _lib.mw_grid.argtypes = [_vp, _PP, _PP, _PP, _i32, _vp]
 _lib.mw_degrid.argtypes = [_vp, _PP, _PP, _PP, _PP, _PP, _vp]
 _lib.mw_image.argtypes = [_vp, _PP, _PP, _i32, _i32, _vp]
+_lib.mw_stokes.argtypes = [_vp, _PP, _PP, _PP, _vp]
 _lib.mw_plan_info.argtypes = [_vp, _i32, ctypes.POINTER(MwPlanStats)]
 _lib.mw_plan_positions.argtypes = [_vp, _i32, _vp]
 _lib.mw_plan_tables.argtypes = [_vp, _i32, _vp, _vp, _vp]
@@ -71,7 +76,7 @@ _lib.mw_abi_version.argtypes = []
 _lib.mw_abi_version.restype = _i32
 for _f in ("mw_grid_plan", "mw_grid", "mw_degrid", "mw_image", "mw_plan_info",
            "mw_plan_positions", "mw_plan_tables", "mw_plan_destroy", "mw_plan_set_timing",
-           "mw_plan_kernel_ms"):
+           "mw_plan_kernel_ms", "mw_stokes"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -368,6 +373,26 @@ class Plan:
         _check(_lib.mw_image(self.handle, ip, op, int(direction), 1 if correct else 0,
                              _stream_handle(stream)))
         return outs if isinstance(x, (list, tuple)) else outs[0]
+
+
+    def stokes(self, images, jones=None, out=None, stream=None):
+        """Stokes I, Q, U, V (float32 [4, ny, nx]) of the XX, XY, YX, YY images; jones: None
+        (ideal feeds) or complex64 [ny, nx, 2, 2] per instance."""
+        import torch
+        x_l, j_l = self._as_list(images), self._as_list(jones)
+        self._check_grid(x_l, "images")
+        outs = (self._as_list(out) if out is not None else
+                [torch.empty((4, sp.ny, sp.nx), dtype=torch.float32, device=self.device)
+                 for sp in self.specs])
+        for i, sp in enumerate(self.specs):
+            self._check_shape(j_l[i], (sp.ny, sp.nx, 2, 2), "jones")
+            self._check_shape(outs[i], (4, sp.ny, sp.nx), "out")
+        ip, _k1 = _ptr_array([_dev_ptr(t, torch.complex64, "images") for t in x_l])
+        jp, _k2 = _ptr_array([_dev_ptr(t, torch.complex64, "jones") for t in j_l])
+        op, _k3 = _ptr_array([_dev_ptr(t, torch.float32, "out") for t in outs])
+        _check(_lib.mw_stokes(self.handle, ip, jp if jones is not None else None, op,
+                              _stream_handle(stream)))
+        return outs if isinstance(images, (list, tuple)) else outs[0]
 
 
 def _grid_image_function():

@@ -466,3 +466,38 @@ def batched_jobs(seed=4001, njobs=96, nmin=1e4, nmax=2e6, fmin=0.05, fmax=0.30,
                 wl.vis = predict_torch(uvw, freq, sky, 1, 0.1, seed * 1000 + j, device)
         jobs.append(wl)
     return jobs
+
+
+# ---------------------------------------------------------------------------------------------
+# Instrument response for the Stokes conversion: a per-pixel 2 x 2 complex Jones matrix that
+# depends on the pixel's direction and on time (hour angle). Synthetic: a smooth dipole-like
+# amplitude pattern per feed, a feed-rotation angle that drifts with hour angle and across
+# the field, small direction-dependent leakage, and a phase screen. Inputs only.
+# ---------------------------------------------------------------------------------------------
+def jones_field(nx, ny, hour_angle=0.0, seed=6001, fov_frac=1.0, dtype=np.complex64):
+    """complex [ny, nx, 2, 2] Jones matrices J(l, m, t), row-major (J00, J01, J10, J11), with
+    l, m the pixel's offsets from the field centre in units of the half field of view."""
+    rng = np.random.default_rng(seed)
+    l = (np.arange(nx) - nx // 2) / (nx / 2) * fov_frac
+    m = (np.arange(ny) - ny // 2) / (ny / 2) * fov_frac
+    L, M = np.meshgrid(l, m)
+    r2 = L * L + M * M
+    # feed amplitudes (never below ~0.35 on the field, so J stays well conditioned)
+    ax = 1.0 - 0.45 * (L * L * 0.9 + M * M * 1.1) / 2.0
+    ay = 1.0 - 0.45 * (L * L * 1.1 + M * M * 0.9) / 2.0
+    c = rng.uniform(-1.0, 1.0, 6)
+    phx = 0.4 * c[0] * L + 0.3 * c[1] * M + 0.1 * hour_angle
+    phy = 0.3 * c[2] * L + 0.4 * c[3] * M - 0.1 * hour_angle
+    chi = 0.5 * hour_angle + 0.15 * c[4] * L - 0.1 * c[5] * M   # feed rotation
+    dxy = 0.04 * (L + 0.5j * M) * (1.0 + 0.2 * r2)
+    dyx = -0.03 * (M - 0.7j * L)
+    gx = ax * np.exp(1j * phx)
+    gy = ay * np.exp(1j * phy)
+    cs, sn = np.cos(chi), np.sin(chi)
+    J = np.empty((ny, nx, 2, 2), dtype=np.complex128)
+    # [[gx, gx dxy], [gy dyx, gy]] @ [[cos chi, sin chi], [-sin chi, cos chi]]
+    J[..., 0, 0] = gx * (cs - dxy * sn)
+    J[..., 0, 1] = gx * (sn + dxy * cs)
+    J[..., 1, 0] = gy * (dyx * cs - sn)
+    J[..., 1, 1] = gy * (dyx * sn + cs)
+    return J.astype(dtype)

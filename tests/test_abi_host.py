@@ -63,7 +63,7 @@ def test_struct_layout_matches_c(mw, tmp_path):
 
 
 def test_abi_version(mw):
-    assert mw.abi_version() == 3
+    assert mw.abi_version() == 4
 
 
 def _instance(mw, **over):
@@ -128,7 +128,9 @@ def test_calls_on_missing_or_dead_plans(mw):
     assert lib.mw_grid(None, None, None, None, 0, None) == 1
     assert lib.mw_degrid(None, None, None, None, None, None, None) == 1
     assert lib.mw_image(None, None, None, 1, 1, None) == 1
+    assert lib.mw_stokes(None, None, None, None, None) == 1
     bogus = ctypes.c_void_p(0x1000)
+    assert lib.mw_stokes(bogus, None, None, None, None) == 5
     assert lib.mw_grid(bogus, None, None, None, 0, None) == 5
     assert b"not live" in lib.mw_last_error()
     assert lib.mw_plan_destroy(bogus) == 5
