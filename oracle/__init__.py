@@ -403,3 +403,113 @@ def stokes(images, jones=None, pixels=None):
             M = Sinv @ np.kron(Ji, np.conj(Ji))
         out[:, k] = M @ e
     return out.real if pixels is not None else out.real.reshape(4, ny, nx)
+
+
+# ---------------------------------------------------------------------------------------------
+# Calibration (Section 2: the complex gain of each antenna from a large linear least-squares
+# fit to observed catalogue sources; Section 2.1: the data are manipulated to measure and then
+# remove the contribution of catalogue sources in decreasing order of predicted flux, each
+# measurement constraining the antenna gains, iteratively; Table 1, "CML").
+# ---------------------------------------------------------------------------------------------
+C_LIGHT = 299_792_458.0
+
+
+def predict(uvw, freq, sources, npol=1):
+    """Visibilities of point sources: V[g, pol] = sum_s S_s exp(-2 pi i (u l_s + v m_s +
+    w (n_s - 1))), n_s = sqrt(1 - l_s^2 - m_s^2), (u, v, w) = uvw * f / c in wavelengths, for
+    group g = row * nchan + chan. Unpolarised sources: every polarisation gets the same value,
+    except the cross polarisations XY, YX (1 and 2 of 4), which are zero.
+
+    sources: float [nsrc, 3] of (l, m, flux). Returns complex128 [nrow * nchan, npol].
+    """
+    uvw = np.asarray(uvw, dtype=np.float64)
+    freq = np.asarray(freq, dtype=np.float64)
+    src = np.asarray(sources, dtype=np.float64).reshape(-1, 3)
+    nrow, nchan = uvw.shape[0], freq.shape[0]
+    base = np.zeros((nrow, nchan), dtype=np.complex128)
+    for l, m, s in src:
+        n1 = np.sqrt(1.0 - l * l - m * m) - 1.0
+        path = uvw[:, 0] * l + uvw[:, 1] * m + uvw[:, 2] * n1          # metres, per row
+        for c in range(nchan):
+            base[:, c] += s * np.exp(-2j * np.pi * path * (freq[c] / C_LIGHT))
+    out = np.zeros((nrow * nchan, npol), dtype=np.complex128)
+    for p in range(npol):
+        if not (npol == 4 and p in (1, 2)):
+            out[:, p] = base.reshape(-1)
+    return out
+
+
+def stefcal(vis, model, ant1, ant2, nant, nchan, g0=None, niter=10, weights=None):
+    """Per-antenna complex gains g with vis ~ g[a1] conj(g[a2]) model, by the alternating
+    least-squares iteration of Salvini & Wijnholds (2014, A&A 571, A97, "StEFCal").
+
+    Every iteration solves, for each antenna p separately and with the other antennas' gains
+    held at the previous iterate, the one-unknown least-squares problem over all samples that
+    involve p. The data are Hermitian in the antenna pair: a sample (a1 = q, a2 = p) is
+    R_qp = V with model M_qp = M, a sample (a1 = p, a2 = q) gives R_qp = conj(V) with
+    M_qp = conj(M), and both read R_qp ~ z_q conj(g_p) with z_q = g_q M_qp. The solution is
+    g_p = sum w z_q conj(R_qp) / sum w |z_q|^2 over all times, channels and polarisations.
+    Every second iteration the new iterate is replaced by the mean of it and the previous one
+    (the method's damping). An antenna with no weight keeps its gain.
+
+    vis, model: complex [nrow * nchan, npol]; ant1, ant2: int [nrow]; weights: real
+    [nrow * nchan] or None (= 1; 0 excludes a sample). Returns (g complex128 [nant],
+    rel_step = ||g_i - g_(i-1)|| / ||g_i|| of the last iteration before any averaging).
+    """
+    V = np.asarray(vis, dtype=np.complex128)
+    M = np.asarray(model, dtype=np.complex128)
+    if V.ndim == 1:
+        V, M = V[:, None], M[:, None]
+    rows = np.arange(V.shape[0]) // nchan
+    a1 = np.asarray(ant1, dtype=np.int64)[rows]
+    a2 = np.asarray(ant2, dtype=np.int64)[rows]
+    w = np.ones(V.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64)
+    g = np.ones(nant, dtype=np.complex128) if g0 is None else np.array(g0, dtype=np.complex128)
+    rel = 0.0
+    for it in range(1, niter + 1):
+        num = np.zeros(nant, dtype=np.complex128)
+        den = np.zeros(nant, dtype=np.float64)
+        for p in range(V.shape[1]):
+            # samples with a1 = p: R_qp = conj(V), M_qp = conj(M), z = g[a2] conj(M)
+            z = g[a2] * np.conj(M[:, p])
+            np.add.at(num, a1, w * z * V[:, p])            # z conj(R) = z V
+            np.add.at(den, a1, w * np.abs(z) ** 2)
+            # samples with a2 = p: R_qp = V, M_qp = M, z = g[a1] M
+            z = g[a1] * M[:, p]
+            np.add.at(num, a2, w * z * np.conj(V[:, p]))
+            np.add.at(den, a2, w * np.abs(z) ** 2)
+        gnew = g.copy()
+        ok = den > 0
+        gnew[ok] = num[ok] / den[ok]
+        nrm = np.linalg.norm(gnew)
+        rel = float(np.linalg.norm(gnew - g) / nrm) if nrm > 0 else 0.0
+        g = 0.5 * (gnew + g) if it % 2 == 0 else gnew
+    return g, rel
+
+
+def peel(vis, uvw, freq, ant1, ant2, nant, sources, npol=1, niter=10, weights=None):
+    """The calibration measurement loop: catalogue sources are taken in decreasing order of
+    their (predicted) flux |S|, ties in catalogue order. For each: predict its visibilities,
+    measure the antenna gains toward it from the current residual data (``stefcal`` from unit
+    gains), and remove it: residual -= g[a1] conj(g[a2]) model.
+
+    Returns (residual complex128 [ngroups, npol], gains complex128 [nsrc, nant] in catalogue
+    order, rel_step [nsrc], order: the processing order of catalogue indices).
+    """
+    R = np.array(vis, dtype=np.complex128)
+    if R.ndim == 1:
+        R = R[:, None]
+    src = np.asarray(sources, dtype=np.float64).reshape(-1, 3)
+    nchan = np.asarray(freq).shape[0]
+    order = sorted(range(src.shape[0]), key=lambda k: -abs(src[k, 2]))
+    rows = np.arange(R.shape[0]) // nchan
+    a1 = np.asarray(ant1, dtype=np.int64)[rows]
+    a2 = np.asarray(ant2, dtype=np.int64)[rows]
+    gains = np.zeros((src.shape[0], nant), dtype=np.complex128)
+    rels = np.zeros(src.shape[0])
+    for k in order:
+        M = predict(uvw, freq, src[k:k + 1], npol=npol)
+        g, rels[k] = stefcal(R, M, ant1, ant2, nant, nchan, niter=niter, weights=weights)
+        gains[k] = g
+        R = R - (g[a1] * np.conj(g[a2]))[:, None] * M
+    return R, gains, rels, order
