@@ -513,3 +513,37 @@ def peel(vis, uvw, freq, ant1, ant2, nant, sources, npol=1, niter=10, weights=No
         gains[k] = g
         R = R - (g[a1] * np.conj(g[a2]))[:, None] * M
     return R, gains, rels, order
+
+
+# ---------------------------------------------------------------------------------------------
+# Density weighting (an imaging variant outside the paper, which grids with the data's own
+# weights): uniform and Briggs robust weights from the summed weight of each grid cell.
+# ---------------------------------------------------------------------------------------------
+def density_weights(pos, keep, nx, ny, weights=None, mode="uniform", robust=0.0):
+    """Weights after density weighting, float64 [ngroups] (0 for dropped groups).
+
+    The density of a cell is the summed natural weight W(c) = sum w_k over the kept groups whose
+    centre cell (cx, cy) is c (the visibilities as given; their Hermitian mirrors are not
+    gridded, so they are not counted). Uniform: w'_k = w_k / W(c_k). Robust (Briggs 1995, with
+    robustness R): f^2 = (5 * 10^-R)^2 / (sum_c W(c)^2 / sum_k w_k) and
+    w'_k = w_k / (1 + W(c_k) f^2); R -> +inf tends to natural weighting, R -> -inf to uniform
+    (up to a constant factor).
+    """
+    pos = np.asarray(pos)
+    keep = np.asarray(keep, dtype=bool)
+    w = np.ones(pos.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64).copy()
+    w = np.where(keep, w, 0.0)
+    cell = np.where(keep, pos[:, 1].astype(np.int64) * nx + pos[:, 0].astype(np.int64), 0)
+    W = np.zeros(nx * ny)
+    for k in np.flatnonzero(keep):           # plain accumulation in input order
+        W[cell[k]] += w[k]
+    out = np.zeros_like(w)
+    kk = keep & (w != 0)
+    if mode == "uniform":
+        out[kk] = w[kk] / W[cell[kk]]
+    elif mode == "robust":
+        f2 = (5.0 * 10.0 ** (-robust)) ** 2 / (np.sum(W * W) / np.sum(w))
+        out[kk] = w[kk] / (1.0 + W[cell[kk]] * f2)
+    else:
+        raise ValueError(mode)
+    return out
