@@ -85,13 +85,15 @@ def _cplx(a):
 # ---------------------------------------------------------------------------------------------
 # Positions, quantisation, keep rule (Section 2.1 "interpolates the samples onto a regular grid")
 # ---------------------------------------------------------------------------------------------
-def positions(uvw, freq, nx, ny, du, dv, W, O, flags=None, weights=None, half=None):
+def positions(uvw, freq, nx, ny, du, dv, W, O, flags=None, weights=None, half=None, wrange=None):
     """Quantised grid position of every (row, channel) group, and the keep mask.
 
     u = (u_m * f)/c, x = u/du + nx/2, qx = floor(x*O + 1/2), cx = floor((qx + O/2)/O),
     px = qx - cx*O (same in y). A group is dropped if it is flagged, has zero weight, or its
     footprint [cx-h, cx+h] x [cy-h, cy+h] leaves the grid. ``half`` gives a per-group half
-    support (kernel stacks); otherwise h = (W-1)/2.
+    support (kernel stacks); otherwise h = (W-1)/2. ``wrange`` = (wlo, whi) keeps only groups
+    with wlo <= w < whi, w = (w_m * f)/c (one plane of w-stacking); the others count as
+    flagged.
 
     Returns (pos int32 [ngroups, 4], keep bool [ngroups], counts dict).
     """
@@ -100,6 +102,10 @@ def positions(uvw, freq, nx, ny, du, dv, W, O, flags=None, weights=None, half=No
     freq = _c(freq, np.float64)
     nrow, nchan = uvw.shape[0], freq.shape[0]
     ng = nrow * nchan
+    if wrange is not None:
+        wl = ((uvw[:, 2:3] * freq[None, :]) / C_LIGHT).reshape(-1)
+        out = ~((wl >= wrange[0]) & (wl < wrange[1]))
+        flags = out if flags is None else (np.asarray(flags).astype(bool) | out)
     flags = _c(flags, np.uint8)
     weights = _c(weights, np.float64)
     half = _c(half, np.int32)
@@ -546,4 +552,25 @@ def density_weights(pos, keep, nx, ny, weights=None, mode="uniform", robust=0.0)
         out[kk] = w[kk] / (1.0 + W[cell[kk]] * f2)
     else:
         raise ValueError(mode)
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# w-stacking (an imaging variant outside the paper, which treats the array as coplanar): the
+# groups are split by w into planes, each gridded and imaged on its own, and the images are
+# summed with the w-term phase of their plane.
+# ---------------------------------------------------------------------------------------------
+def wstack_combine(images, wplanes, du, dv):
+    """I[p] = sum_k images_k[p] exp(+2 pi i w_k (n - 1)) at each pixel, with
+    l = (x - nx/2) / (nx du), m = (y - ny/2) / (ny dv), n = sqrt(1 - l^2 - m^2) (0 outside
+    the unit circle). images: complex [nplanes, npol, ny, nx]; wplanes: [nplanes] (the w of
+    each plane, in wavelengths)."""
+    z = np.asarray(images, dtype=np.complex128)
+    nplanes, npol, ny, nx = z.shape
+    l = (np.arange(nx) - nx // 2) / (nx * du)
+    m = (np.arange(ny) - ny // 2) / (ny * dv)
+    n = np.sqrt(np.maximum(0.0, 1.0 - l[None, :] ** 2 - m[:, None] ** 2))
+    out = np.zeros((npol, ny, nx), dtype=np.complex128)
+    for k in range(nplanes):
+        out += z[k] * np.exp(2j * np.pi * wplanes[k] * (n - 1.0))[None]
     return out
