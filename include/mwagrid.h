@@ -167,6 +167,23 @@ mw_status mw_grid(mw_plan plan, const void *const *vis, const void *const *gains
                   void *const *grid, int32_t accumulate, void *stream);
 
 /*
+ * Grid without allocating: for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc). Computes exactly what
+ * mw_grid computes, with the same kernels and summation order (identical bits), but the merge
+ * flush's partial tiles live in the library's static device scratch array of 192 MiB (one per
+ * GPU, held until the process ends) instead of plan-owned memory that mw_grid may allocate on
+ * its first call. The call allocates nothing and frees nothing. A plan whose merge flush needs
+ * more than 192 MiB of partial tiles (2 * npol * (tile + W - 1)^2 floats per work item) is
+ * refused with MW_ERR_UNSUPPORTED. Instances run one after another in stream order (a batched
+ * plan's graph is not used). The scratch holds no state between calls (every partial tile is
+ * written before it is read), but all calls on one GPU share it: calls that overlap in time
+ * on one GPU (different streams or threads) race and must be serialised by the caller.
+ * Errors: as mw_grid, plus MW_ERR_UNSUPPORTED (scratch too small).
+ */
+mw_status mw_grid_noalloc(mw_plan plan, const void *const *vis, const void *const *gains,
+                          void *const *grid, int32_t accumulate, void *stream);
+
+/*
  * Degrid, the exact adjoint of mw_grid: for every instance and kept group,
  *   vis_out[g][pol] = w * conj(g[ant1]) * g[ant2] * sum_taps conj?(tap) * grid[pol][cell]
  * (conjugated taps for stacks), and 0 for dropped groups. vis_out is overwritten.

@@ -11,9 +11,22 @@
 #include <set>
 #include <string>
 
+// Scratch of the no-allocation gridding entry point (mw_grid_noalloc): the merge flush's
+// partial tiles, in a file-scope device array instead of plan-owned memory. Every device the
+// library runs on holds its own copy until the process ends; the host never uses the array's
+// name as an address (it is a host-side stand-in), only the per-device address looked up with
+// hipGetSymbolAddress below.
+constexpr size_t kScratchBytes = size_t(192) << 20;
+static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+// Per-device address of scratch, looked up once per device with that device current.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
 
 // Live plans: a handle that was destroyed (or never made) is rejected instead of used.
 std::mutex g_plans_mu;
@@ -107,6 +120,26 @@ void destroy_plan(mwg::Plan *P) {
 }
 
 } // namespace
+
+namespace mwg {
+
+Status static_scratch(void **ptr, size_t *bytes) {
+    int dev = -1;
+    MWG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return make_error(MW_ERR_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        MWG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return make_error(MW_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *bytes = kScratchBytes;
+    return Status::Ok();
+}
+
+} // namespace mwg
 
 
 extern "C" {
@@ -203,6 +236,40 @@ mw_status mw_grid(mw_plan plan, const void *const *vis, const void *const *gains
         return ok();
     } catch (...) {
         return fail(MW_ERR_HIP, "unexpected exception in mw_grid");
+    }
+}
+
+mw_status mw_grid_noalloc(mw_plan plan, const void *const *vis, const void *const *gains, void *const *grid,
+                          int32_t accumulate, void *stream) {
+    try {
+        mwg::Status s = check_plan(plan);
+        if (!s.ok()) return fail(s);
+        if (!vis || !grid) return fail(MW_ERR_INVALID_ARG, "vis and grid arrays are required");
+        mwg::Plan *P = (mwg::Plan *)plan;
+        const int n = (int)P->inst.size();
+        for (int i = 0; i < n; i++) {
+            if (!grid[i] || (!vis[i] && P->inst[i]->ngroups > 0))
+                return fail(MW_ERR_INVALID_ARG, "vis[i] and grid[i] must be device pointers");
+            const uintptr_t align = P->inst[i]->npol >= 2 ? 16 : 8;
+            if (((uintptr_t)vis[i] % align) || ((uintptr_t)grid[i] % 8))
+                return fail(MW_ERR_INVALID_ARG, "vis must be 16-byte aligned (8 for npol 1), grid 8-byte");
+            if (gains && gains[i] && !P->inst[i]->has_ants)
+                return fail(MW_ERR_STATE, "gains given for an instance planned without antennas");
+        }
+        void *scr = nullptr;
+        size_t cap = 0;
+        s = mwg::static_scratch(&scr, &cap);
+        if (!s.ok()) return fail(s);
+        // instance by instance in stream order (a batched plan too: its graph is not used), each
+        // reusing the whole scratch array
+        for (int i = 0; i < n; i++) {
+            s = mwg::launch_grid_into(*P->inst[i], (const float2 *)vis[i], gains ? (const float2 *)gains[i] : nullptr,
+                                      (float2 *)grid[i], accumulate ? 1 : 0, (float *)scr, cap, (hipStream_t)stream);
+            if (!s.ok()) return fail(s);
+        }
+        return ok();
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_grid_noalloc");
     }
 }
 

@@ -578,14 +578,24 @@ __global__ __launch_bounds__(kMergeB * kMergeB) void k_merge(float2 *grid, const
 }
 
 template <int NPOL>
-Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s) {
+Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s, float *partial_in = nullptr,
+                        size_t partial_cap = 0) {
     const Launch &L = I.L;
     const int R = L.tile + I.W - 1;
     a.str = L.variant == 4 ? R : tile_stride(R, I.W);
     a.plane = (L.variant == 2 || L.variant == 4) ? tile_plane2(R, a.str, I.W) : tile_plane(R, a.str);
     const int flush = L.flush;
-    if (flush == 2) MWG_TRY(ensure_partial(I, s));
-    a.partial = I.partial;
+    if (partial_in) {
+        const size_t need = sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * I.npol * R * R;
+        if (flush == 2 && need > partial_cap)
+            return make_error(MW_ERR_UNSUPPORTED,
+                              "the merge flush of this plan needs %zu B of scratch, more than the %zu B available",
+                              need, partial_cap);
+        a.partial = partial_in;
+    } else {
+        if (flush == 2) MWG_TRY(ensure_partial(I, s));
+        a.partial = I.partial;
+    }
     int nwork = I.nwork;
     if (flush == 3) {
         // owner tiles: the work list, codes and sorted arrays of the (output tile, group) pairs
@@ -658,7 +668,7 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s)
         if (I.n_mblocks + nzero > 0) {
             const int chunk = (I.n_mblocks + 7) / 8;
             hipLaunchKernelGGL(k_merge<NPOL>, dim3(8 * chunk + nzero), dim3(kMergeB * kMergeB), 0, s, a.grid,
-                               (const float *)I.partial, (const int32_t *)I.tile_work, (const int32_t *)I.work_ids,
+                               (const float *)a.partial, (const int32_t *)I.tile_work, (const int32_t *)I.work_ids,
                                (const int32_t *)I.mblocks, I.n_mblocks, nzero, I.nx, I.ny, ilog2(L.tile), I.ntx,
                                I.nty, I.W, accumulate);
             MWG_HIP(hipGetLastError());
@@ -728,6 +738,11 @@ Status launch_fill_zero(void *ptr, size_t nbytes, hipStream_t s) {
 
 Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *grid, int accumulate,
                    hipStream_t s) {
+    return launch_grid_into(I, vis, gains, grid, accumulate, nullptr, 0, s);
+}
+
+Status launch_grid_into(Instance &I, const float2 *vis, const float2 *gains, float2 *grid, int accumulate,
+                        float *partial, size_t partial_cap, hipStream_t s) {
     if (I.stacks) return launch_grid_stack(I, vis, gains, grid, accumulate, s);
     GridArgs a{};
     a.vis = vis;
@@ -753,9 +768,9 @@ Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *
     a.W = I.W;
     a.O = I.O;
     switch (I.npol) {
-    case 1: return launch_grid_npol<1>(I, a, accumulate, s);
-    case 2: return launch_grid_npol<2>(I, a, accumulate, s);
-    case 4: return launch_grid_npol<4>(I, a, accumulate, s);
+    case 1: return launch_grid_npol<1>(I, a, accumulate, s, partial, partial_cap);
+    case 2: return launch_grid_npol<2>(I, a, accumulate, s, partial, partial_cap);
+    case 4: return launch_grid_npol<4>(I, a, accumulate, s, partial, partial_cap);
     default: return make_error(MW_ERR_UNSUPPORTED, "npol %d", I.npol);
     }
 }

@@ -183,6 +183,13 @@ size_t stack_lds(int npol, int T, int waves);
 // grid.hip
 Status launch_grid(Instance &I, const float2 *vis, const float2 *gains, float2 *grid,
                    int accumulate, hipStream_t s);
+// The same launch with the merge flush's partial tiles in caller-given device memory of
+// partial_cap bytes (no allocation; MW_ERR_UNSUPPORTED if the plan needs more).
+Status launch_grid_into(Instance &I, const float2 *vis, const float2 *gains, float2 *grid, int accumulate,
+                        float *partial, size_t partial_cap, hipStream_t s);
+// Device address of the library's static scratch array on the current device (looked up once
+// per device) and its size in bytes.
+Status static_scratch(void **ptr, size_t *bytes);
 Status launch_fill_zero(void *ptr, size_t nbytes, hipStream_t s);
 
 // degrid.hip

@@ -60,6 +60,7 @@ _PP = ctypes.POINTER(ctypes.c_void_p)
 _lib.mw_grid_plan.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(MwInstance), _i32,
                               ctypes.POINTER(MwTuning), _vp]
 _lib.mw_grid.argtypes = [_vp, _PP, _PP, _PP, _i32, _vp]
+_lib.mw_grid_noalloc.argtypes = [_vp, _PP, _PP, _PP, _i32, _vp]
 _lib.mw_degrid.argtypes = [_vp, _PP, _PP, _PP, _PP, _PP, _vp]
 _lib.mw_image.argtypes = [_vp, _PP, _PP, _i32, _i32, _vp]
 _lib.mw_stokes.argtypes = [_vp, _PP, _PP, _PP, _vp]
@@ -76,7 +77,7 @@ _lib.mw_abi_version.argtypes = []
 _lib.mw_abi_version.restype = _i32
 for _f in ("mw_grid_plan", "mw_grid", "mw_degrid", "mw_image", "mw_plan_info",
            "mw_plan_positions", "mw_plan_tables", "mw_plan_destroy", "mw_plan_set_timing",
-           "mw_plan_kernel_ms", "mw_stokes"):
+           "mw_plan_kernel_ms", "mw_stokes", "mw_grid_noalloc"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -318,7 +319,9 @@ class Plan:
         return [torch.empty((sp.npol, sp.ny, sp.nx), dtype=torch.complex64, device=self.device)
                 for sp in self.specs]
 
-    def grid(self, vis, gains=None, out=None, accumulate=False, stream=None):
+    def grid(self, vis, gains=None, out=None, accumulate=False, stream=None, noalloc=False):
+        """mw_grid; noalloc=True calls mw_grid_noalloc (static scratch, no allocation; out
+        should then be given so that the binding allocates nothing either)."""
         import torch
         vis_l, gains_l = self._as_list(vis), self._as_list(gains)
         outs = self._as_list(out) if out is not None else self.new_grids()
@@ -328,8 +331,9 @@ class Plan:
         vp, _k1 = _ptr_array([_dev_ptr(v, torch.complex64, "vis") for v in vis_l])
         gp, _k2 = _ptr_array([_dev_ptr(g, torch.complex64, "gains") for g in gains_l])
         op, _k3 = _ptr_array([_dev_ptr(o, torch.complex64, "grid") for o in outs])
-        _check(_lib.mw_grid(self.handle, vp, gp if gains is not None else None, op,
-                            1 if accumulate else 0, _stream_handle(stream)))
+        fn = _lib.mw_grid_noalloc if noalloc else _lib.mw_grid
+        _check(fn(self.handle, vp, gp if gains is not None else None, op,
+                  1 if accumulate else 0, _stream_handle(stream)))
         return outs if isinstance(vis, (list, tuple)) else outs[0]
 
     def degrid(self, grid, gains=None, vis_in=None, want_grad_gains=False, out=None,
