@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MW_ABI_VERSION 4
+#define MW_ABI_VERSION 5
 
 typedef enum {
     MW_OK = 0,
@@ -88,6 +88,19 @@ typedef struct {
     int64_t kernel_elems;         /* complex elements in kernel_stack */
     const int32_t *kernel_index;  /* [ngroups] */
     int32_t mem;                  /* MW_MEM_HOST or MW_MEM_DEVICE for all arrays above */
+    /* Density weighting (an imaging variant; the paper grids with the data's own weights):
+     * 0 = natural (the weights as given), 1 = uniform, 2 = Briggs robust with robustness
+     * "robust". The density of a cell is the summed weight W(c) of the kept groups centred in
+     * it; uniform: w / W(c); robust: w / (1 + W(c) f^2), f^2 = (5 * 10^-R)^2 /
+     * (sum_c W(c)^2 / sum w). The resulting weights replace the given ones in every later
+     * call (grid, degrid). Cell sums are exact fixed-point integers (order-independent). */
+    int32_t weighting;
+    float robust;
+    /* w-stacking (an imaging variant; the paper treats the array as coplanar): with
+     * wlo < whi the instance grids only groups with wlo <= w < whi, w = (w_m * f) / 299792458
+     * in FP64 (the others count as flagged), and the plane's w is (wlo + whi) / 2 in
+     * mw_wstack_combine. wlo = whi = 0: no selection. */
+    double wlo, whi;
 } mw_instance;
 
 /* Optional launch choices. Zero fields mean "choose automatically". */
@@ -230,6 +243,68 @@ mw_status mw_image(mw_plan plan, const void *const *in, void *const *out, int32_
  */
 mw_status mw_stokes(mw_plan plan, const void *const *images, const void *const *jones,
                     void *const *out, void *stream);
+
+/*
+ * Calibration (Section 2: the complex gain of each antenna from a linear least-squares fit to
+ * observed catalogue sources; Section 2.1: the contribution of catalogue sources is measured
+ * and removed in decreasing order of predicted flux, each measurement constraining the antenna
+ * gains, iteratively; Table 1, "CML"). These calls use the instance's uvw and frequencies as
+ * planned, every group (flags and the grid's footprint rule do not apply; pass zero weights to
+ * exclude samples) and scalar gains per antenna shared by all polarisations.
+ *
+ * mw_predict: vis = (or +=, accumulate = 1) sum over sources of S exp(-2 pi i (u l + v m +
+ * w (n - 1))), n = sqrt(1 - l^2 - m^2), (u, v, w) = uvw * f / 299792458, times
+ * g[a1] conj(g[a2]) if gains is given (device complex64 [nant]; needs antennas). Unpolarised
+ * sources: with 4 polarisations the cross terms XY, YX (1, 2) are zero. sources: device
+ * float64 [nsrc][3] = (l, m, S). vis: device complex64 [ngroups][npol]. Phases in FP64, reduced
+ * to a fraction of a turn before FP32 sine and cosine; FP32 sums.
+ */
+mw_status mw_predict(mw_plan plan, int32_t inst, const double *sources, int32_t nsrc,
+                     const void *gains, void *vis, int32_t accumulate, void *stream);
+
+/*
+ * mw_solve_gains: per-antenna complex gains g with vis ~ g[a1] conj(g[a2]) model, by niter
+ * iterations of the alternating least-squares method of Salvini & Wijnholds (2014,
+ * "StEFCal"): each iteration solves every antenna's gain with the others at the previous
+ * iterate, g_p = sum w z conj(R) / sum w |z|^2 over the samples involving p, and every second
+ * iterate is averaged with the previous one. gains: device complex64 [nant], the starting
+ * point in, the solution out (an antenna without weighted samples keeps its value). vis,
+ * model: device complex64 [ngroups][npol]; weights: device float32 [ngroups] or NULL (= 1).
+ * rel_step: device float32 [1] or NULL, receives ||g_i - g_(i-1)|| / ||g_i|| of the last
+ * iteration. Needs an instance planned with antennas (else MW_ERR_STATE).
+ */
+mw_status mw_solve_gains(mw_plan plan, int32_t inst, const void *vis, const void *model,
+                         const float *weights, void *gains, int32_t niter, float *rel_step,
+                         void *stream);
+
+/*
+ * mw_peel: the measurement loop. Sources (host float64 [nsrc][3] = (l, m, S), read before the
+ * call returns) are taken in decreasing |S|, ties in catalogue order. For each: the gains
+ * toward it are solved (mw_solve_gains from unit gains, niter >= 1 iterations) from the current
+ * residual against its prediction, and g[a1] conj(g[a2]) times the prediction is removed from
+ * the residual. resid: device complex64 [ngroups][npol] (may equal vis; starts as vis);
+ * gains: device complex64 [nsrc][nant], row k for catalogue entry k; rel_step: device float32
+ * [nsrc] or NULL. The plan keeps a device and a pinned host copy of the catalogue (grown on
+ * demand). Needs an instance planned with antennas.
+ */
+mw_status mw_peel(mw_plan plan, int32_t inst, const void *vis, const double *sources, int32_t nsrc,
+                  const float *weights, int32_t niter, void *resid, void *gains, float *rel_step,
+                  void *stream);
+
+/*
+ * w-stacking: the images of a plan's instances, one w-plane each (every instance with a
+ * w-range, the same grid size, cell size and polarisations), summed with the w-term of their
+ * plane: out[p] (+)= sum_k images[k][p] exp(+2 pi i w_k (n - 1)) at every pixel, with
+ * w_k = (wlo + whi) / 2 of instance k, l = (x - nx/2) / (nx du), m = (y - ny/2) / (ny dv),
+ * n = sqrt(1 - l^2 - m^2) (0 outside the unit circle). The images come from mw_image of each
+ * plane's grid (with the convolution correction if wanted). images[k]: device complex64
+ * [npol][ny][nx]; out: device complex64 [npol][ny][nx] (accumulate = 0 overwrites). At most 64
+ * planes per call. Phases in FP64, reduced to a fraction of a turn before FP32 sine and
+ * cosine. Errors: MW_ERR_INVALID_ARG, MW_ERR_STATE (an instance without a w-range, or
+ * instances of different shapes), MW_ERR_UNSUPPORTED (more than 64 planes), MW_ERR_HIP.
+ */
+mw_status mw_wstack_combine(mw_plan plan, const void *const *images, void *out, int32_t accumulate,
+                            void *stream);
 
 /* Statistics and chosen launch of instance inst (inst = -1: sums over instances). */
 mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out);

@@ -65,6 +65,10 @@ mwg::Status validate_instance(const mw_instance &d, int idx) {
         return make_error(MW_ERR_UNSUPPORTED, "instance %d: nrow * nchan must be < 2^31", idx);
     if (d.npol != 1 && d.npol != 2 && d.npol != 4) return bad("npol must be 1, 2 or 4");
     if (d.mem != MW_MEM_HOST && d.mem != MW_MEM_DEVICE) return bad("mem must be MW_MEM_HOST or MW_MEM_DEVICE");
+    if (d.weighting < 0 || d.weighting > 2) return bad("weighting must be 0 (natural), 1 (uniform) or 2 (robust)");
+    if (!std::isfinite(d.robust)) return bad("robust must be finite");
+    if (!std::isfinite(d.wlo) || !std::isfinite(d.whi) || d.wlo > d.whi) return bad("need finite wlo <= whi");
+    if (d.weighting != 0 && d.kernel_stack) return bad("density weighting is implemented for the built-in kernel");
     if (d.nrow > 0 && (!d.uvw_m || !d.freq_hz)) return bad("uvw_m and freq_hz are required");
     if ((d.ant1 == nullptr) != (d.ant2 == nullptr)) return bad("ant1 and ant2 go together");
     if (d.ant1 && (d.nant < 1 || d.nant > 65535)) return bad("nant must be in [1, 65535]");
@@ -111,6 +115,8 @@ void destroy_plan(mwg::Plan *P) {
         if (!I) continue;
         for (hipEvent_t &e : I->tev)
             if (e) (void)hipEventDestroy(e);
+        if (I->src_ev) (void)hipEventDestroy(I->src_ev);
+        if (I->src_h) (void)hipHostFree(I->src_h);
         mwg::image_release(*I);
         I->arena.release();
         delete I;
@@ -355,6 +361,82 @@ mw_status mw_stokes(mw_plan plan, const void *const *images, const void *const *
         return ok();
     } catch (...) {
         return fail(MW_ERR_HIP, "unexpected exception in mw_stokes");
+    }
+}
+
+namespace {
+mwg::Status check_inst(mw_plan plan, int32_t inst, mwg::Instance **out) {
+    mwg::Status s = check_plan(plan);
+    if (!s.ok()) return s;
+    mwg::Plan *P = (mwg::Plan *)plan;
+    if (inst < 0 || inst >= (int)P->inst.size()) return mwg::make_error(MW_ERR_INVALID_ARG, "inst out of range");
+    *out = P->inst[inst];
+    return mwg::Status::Ok();
+}
+} // namespace
+
+mw_status mw_predict(mw_plan plan, int32_t inst, const double *sources, int32_t nsrc, const void *gains, void *vis,
+                     int32_t accumulate, void *stream) {
+    try {
+        mwg::Instance *I = nullptr;
+        mwg::Status s = check_inst(plan, inst, &I);
+        if (!s.ok()) return fail(s);
+        if ((!vis && I->ngroups > 0) || (!sources && nsrc > 0))
+            return fail(MW_ERR_INVALID_ARG, "vis and sources must be device pointers");
+        s = mwg::launch_predict(*I, sources, nsrc, (const float2 *)gains, (float2 *)vis, accumulate ? 1 : 0,
+                                (hipStream_t)stream);
+        return s.ok() ? ok() : fail(s);
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_predict");
+    }
+}
+
+mw_status mw_solve_gains(mw_plan plan, int32_t inst, const void *vis, const void *model, const float *weights,
+                         void *gains, int32_t niter, float *rel_step, void *stream) {
+    try {
+        mwg::Instance *I = nullptr;
+        mwg::Status s = check_inst(plan, inst, &I);
+        if (!s.ok()) return fail(s);
+        if (!I->has_ants) return fail(MW_ERR_STATE, "gain solving needs an instance planned with antennas");
+        if (!gains || ((!vis || !model) && I->ngroups > 0))
+            return fail(MW_ERR_INVALID_ARG, "vis, model and gains must be device pointers");
+        s = mwg::launch_solve_gains(*I, (const float2 *)vis, (const float2 *)model, weights, (float2 *)gains, niter,
+                                    rel_step, (hipStream_t)stream);
+        return s.ok() ? ok() : fail(s);
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_solve_gains");
+    }
+}
+
+mw_status mw_peel(mw_plan plan, int32_t inst, const void *vis, const double *sources, int32_t nsrc,
+                  const float *weights, int32_t niter, void *resid, void *gains, float *rel_step, void *stream) {
+    try {
+        mwg::Instance *I = nullptr;
+        mwg::Status s = check_inst(plan, inst, &I);
+        if (!s.ok()) return fail(s);
+        if (!I->has_ants) return fail(MW_ERR_STATE, "peeling needs an instance planned with antennas");
+        if (((!vis || !resid) && I->ngroups > 0) || (nsrc > 0 && (!sources || !gains)))
+            return fail(MW_ERR_INVALID_ARG, "vis, resid, gains (device) and sources (host) are required");
+        s = mwg::launch_peel(*I, (const float2 *)vis, sources, nsrc, weights, niter, (float2 *)resid, (float2 *)gains,
+                             rel_step, (hipStream_t)stream);
+        return s.ok() ? ok() : fail(s);
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_peel");
+    }
+}
+
+mw_status mw_wstack_combine(mw_plan plan, const void *const *images, void *out, int32_t accumulate, void *stream) {
+    try {
+        mwg::Status s = check_plan(plan);
+        if (!s.ok()) return fail(s);
+        mwg::Plan *P = (mwg::Plan *)plan;
+        if (!images || !out) return fail(MW_ERR_INVALID_ARG, "images and out are required");
+        for (size_t i = 0; i < P->inst.size(); i++)
+            if (!images[i]) return fail(MW_ERR_INVALID_ARG, "images[i] must be device pointers");
+        s = mwg::launch_wstack_combine(*P, images, (float2 *)out, accumulate ? 1 : 0, (hipStream_t)stream);
+        return s.ok() ? ok() : fail(s);
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception in mw_wstack_combine");
     }
 }
 

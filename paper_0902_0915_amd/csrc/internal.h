@@ -149,6 +149,21 @@ struct Instance {
     int64_t npairs = 0;
     int64_t *koff = nullptr;
     int32_t *ksup = nullptr;
+    // w-stacking: the instance grids only groups with wlo <= w < whi (wavelengths)
+    bool wsel = false;
+    double wlo = 0, whi = 0;
+    // prediction and calibration (calib.hip)
+    double *uvw_d = nullptr;      // [nrow][3] metres
+    double *freq_d = nullptr;     // [nchan] Hz
+    int32_t *cal_start = nullptr; // [nant + 1] CSR of each antenna's rows
+    int32_t *cal_entry = nullptr; // [2 nrow] row << 1 | (0: the row's ant1, 1: its ant2)
+    float4 *cal_pq = nullptr;     // [nrow] per-row sums (Re P, Im P, Q, 0)
+    float2 *cal_g = nullptr;      // [nant] second gain buffer of the iteration
+    double *cal_red = nullptr;    // [2 nant] per-antenna |step|^2 and |g|^2 of the last iteration
+    void *src_d = nullptr, *src_h = nullptr;  // source table, device and pinned host staging
+    size_t src_cap = 0;
+    hipEvent_t src_ev = nullptr;  // guards src_h until its upload has read it
+    bool src_pending = false;
     // host copies for export
     std::vector<float> h_tab, h_corrx, h_corry;
     // image plans (rocFFT); opaque here
@@ -209,6 +224,22 @@ Status launch_fft2d(const float2 *in, float2 *out, int nx, int ny, int npol, con
 Status launch_image_scale(const float2 *in, float2 *out, int nx, int ny, int npol,
                           const float *corrx, const float *corry, int checker, int divide,
                           hipStream_t s);
+
+// calib.hip
+Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_dev, const int32_t *a1_dev,
+                         const int32_t *a2_dev, hipStream_t s);
+Status launch_predict(Instance &I, const double *sources, int nsrc, const float2 *gains, float2 *out,
+                      int accumulate, hipStream_t s);
+Status launch_solve_gains(Instance &I, const float2 *vis, const float2 *model, const float *weights, float2 *gains,
+                          int niter, float *rel, hipStream_t s);
+Status launch_peel(Instance &I, const float2 *vis, const double *sources_host, int nsrc, const float *weights,
+                   int niter, float2 *resid, float2 *gains, float *rel, hipStream_t s);
+
+// wstack.hip
+Status launch_wstack_combine(Plan &P, const void *const *images, float2 *out, int accumulate, hipStream_t s);
+
+// weighting.hip
+Status apply_density_weighting(Instance &I, int mode, float robust, const float *w_in, float *w_out, hipStream_t s);
 
 // owner.hip
 Status build_owner_schedule(Instance &I, int64_t cap, bool *built, hipStream_t s);

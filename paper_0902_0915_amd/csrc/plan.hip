@@ -86,6 +86,8 @@ struct PosArgs {
     const int32_t *ksup;   // stacks: support of each kernel
     uint32_t *pos;
     uint32_t *blk_counts;  // [gridDim.x][3]: kept, flagged, outside of each block
+    int wsel;              // keep only wlo <= w < whi (one plane of w-stacking)
+    double wlo, whi;
 };
 
 __global__ void k_positions(PosArgs a) {
@@ -94,12 +96,17 @@ __global__ void k_positions(PosArgs a) {
     int status = 3; // 0 kept, 1 flagged, 2 outside, 3 out of range
     if (g < a.ngroups) {
         uint32_t packed = kDropped;
-        if ((a.flags && a.flags[g]) || (a.weights && a.weights[g] == 0.0f)) {
+        const int64_t r = g / a.nchan;
+        const int ch = (int)(g - r * a.nchan);
+        const double f = a.freq[ch];
+        bool deselected = false;
+        if (a.wsel) {
+            const double w = (a.uvw[3 * r + 2] * f) / 299792458.0;
+            deselected = !(w >= a.wlo && w < a.whi);
+        }
+        if ((a.flags && a.flags[g]) || (a.weights && a.weights[g] == 0.0f) || deselected) {
             status = 1;
         } else {
-            const int64_t r = g / a.nchan;
-            const int ch = (int)(g - r * a.nchan);
-            const double f = a.freq[ch];
             const double u = (a.uvw[3 * r + 0] * f) / 299792458.0;
             const double v = (a.uvw[3 * r + 1] * f) / 299792458.0;
             const double x = u / a.du + (double)(a.nx / 2);
@@ -929,6 +936,12 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     a.ksup = ksup;
     a.pos = I.pos;
     a.blk_counts = counts.as<uint32_t>() + 6;
+    a.wsel = d.wlo < d.whi ? 1 : 0;
+    a.wlo = d.wlo;
+    a.whi = d.whi;
+    I.wsel = a.wsel != 0;
+    I.wlo = d.wlo;
+    I.whi = d.whi;
     if (ng > 0) {
         hipLaunchKernelGGL(k_positions, dim3(grid1d(ng)), dim3(kBlock), 0, s, a);
         MWG_HIP(hipGetLastError());
@@ -948,6 +961,15 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(ng, 1)));
         I.w_orig = (float *)p;
         if (ng > 0) MWG_HIP(hipMemcpyAsync(I.w_orig, weights, 4 * ng, hipMemcpyDeviceToDevice, s));
+    }
+    if (d.weighting != 0) {
+        // density weighting: the weights every later call uses
+        if (!I.w_orig) {
+            MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(ng, 1)));
+            I.w_orig = (float *)p;
+        }
+        MWG_TRY(apply_density_weighting(I, d.weighting, d.robust, weights, I.w_orig, s));
+        I.has_weights = true;
     }
     if (I.has_ants) {
         MWG_TRY(I.arena.alloc(&p, 4 * (size_t)std::max<int64_t>(I.nrow, 1)));
@@ -990,6 +1012,9 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     I.flush_fixed = tuning && tuning->flush != 0;
     MWG_TRY(rebuild_schedule(I, L, s));
     if (I.stacks) MWG_TRY(build_stack_schedule(I, L, s));
+
+    // prediction and calibration state (uvw, frequencies, per-antenna row lists)
+    MWG_TRY(build_calibration(I, uvw, freq, a1, a2, s));
 
     // A3: kernel tables (built-in kernel) and correction vectors
     if (!I.stacks) {

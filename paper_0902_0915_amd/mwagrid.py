@@ -41,7 +41,8 @@ class MwInstance(ctypes.Structure):
                 ("support", _i32), ("oversample", _i32),
                 ("kernel_stack", _vp), ("kernel_offset", _vp), ("kernel_support", _vp),
                 ("nkernel", _i32), ("kernel_elems", _i64), ("kernel_index", _vp),
-                ("mem", _i32)]
+                ("mem", _i32), ("weighting", _i32), ("robust", ctypes.c_float),
+                ("wlo", ctypes.c_double), ("whi", ctypes.c_double)]
 
 
 class MwTuning(ctypes.Structure):
@@ -64,6 +65,10 @@ _lib.mw_grid_noalloc.argtypes = [_vp, _PP, _PP, _PP, _i32, _vp]
 _lib.mw_degrid.argtypes = [_vp, _PP, _PP, _PP, _PP, _PP, _vp]
 _lib.mw_image.argtypes = [_vp, _PP, _PP, _i32, _i32, _vp]
 _lib.mw_stokes.argtypes = [_vp, _PP, _PP, _PP, _vp]
+_lib.mw_predict.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp, _i32, _vp]
+_lib.mw_solve_gains.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp]
+_lib.mw_peel.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp]
+_lib.mw_wstack_combine.argtypes = [_vp, _PP, _vp, _i32, _vp]
 _lib.mw_plan_info.argtypes = [_vp, _i32, ctypes.POINTER(MwPlanStats)]
 _lib.mw_plan_positions.argtypes = [_vp, _i32, _vp]
 _lib.mw_plan_tables.argtypes = [_vp, _i32, _vp, _vp, _vp]
@@ -77,7 +82,8 @@ _lib.mw_abi_version.argtypes = []
 _lib.mw_abi_version.restype = _i32
 for _f in ("mw_grid_plan", "mw_grid", "mw_degrid", "mw_image", "mw_plan_info",
            "mw_plan_positions", "mw_plan_tables", "mw_plan_destroy", "mw_plan_set_timing",
-           "mw_plan_kernel_ms", "mw_stokes", "mw_grid_noalloc"):
+           "mw_plan_kernel_ms", "mw_stokes", "mw_grid_noalloc", "mw_predict", "mw_solve_gains",
+           "mw_peel", "mw_wstack_combine"):
     getattr(_lib, _f).restype = _i32
 
 
@@ -146,6 +152,9 @@ class InstanceSpec:
     kernel_offset: object = None   # int64 [nkernel]
     kernel_support: object = None  # int32 [nkernel]
     kernel_index: object = None    # int32 [ngroups]
+    weighting: str = "natural"     # "natural", "uniform" or "robust"
+    robust: float = 0.0            # Briggs robustness for "robust"
+    wrange: tuple = (0.0, 0.0)     # (wlo, whi): grid only wlo <= w < whi (one w-plane)
 
     @classmethod
     def from_workload(cls, wl, with_ants=True, with_weights=True):
@@ -193,6 +202,9 @@ def _instance_struct(spec):
         d.kernel_support, d.nkernel = p(a["kernel_support"]), a["kernel_support"].shape[0]
         d.kernel_elems, d.kernel_index = a["kernel_stack"].shape[0], p(a["kernel_index"])
     d.mem = MW_MEM_HOST
+    d.weighting = {"natural": 0, "uniform": 1, "robust": 2}[spec.weighting]
+    d.robust = float(spec.robust)
+    d.wlo, d.whi = float(spec.wrange[0]), float(spec.wrange[1])
     return d, a
 
 
@@ -397,6 +409,93 @@ class Plan:
         _check(_lib.mw_stokes(self.handle, ip, jp if jones is not None else None, op,
                               _stream_handle(stream)))
         return outs if isinstance(images, (list, tuple)) else outs[0]
+
+
+    # ---- calibration ----------------------------------------------------------------------
+    def predict(self, sources, gains=None, out=None, accumulate=False, inst=0, stream=None):
+        """Visibilities of point sources (device float64 [nsrc, 3] of l, m, flux) at the
+        instance's uvw and frequencies, times g1 conj(g2) when gains are given."""
+        import torch
+        sp = self.specs[inst]
+        src = torch.as_tensor(sources, dtype=torch.float64).reshape(-1, 3).contiguous().to(self.device)
+        if out is None:
+            out = torch.empty((self._ngroups(inst), sp.npol), dtype=torch.complex64, device=self.device)
+        self._check_shape(out, (self._ngroups(inst), sp.npol), "out")
+        if gains is not None:
+            self._check_shape(gains, (sp.nant,), "gains")
+        _check(_lib.mw_predict(self.handle, inst, _dev_ptr(src, torch.float64, "sources"), src.shape[0],
+                               _dev_ptr(gains, torch.complex64, "gains"),
+                               _dev_ptr(out, torch.complex64, "out"), 1 if accumulate else 0,
+                               _stream_handle(stream)))
+        return out
+
+    def solve_gains(self, vis, model, weights=None, gains=None, niter=10, inst=0, stream=None):
+        """StEFCal solution of vis ~ g1 conj(g2) model; returns (gains, relative last step)."""
+        import torch
+        sp = self.specs[inst]
+        shape = (self._ngroups(inst), sp.npol)
+        self._check_shape(vis, shape, "vis")
+        self._check_shape(model, shape, "model")
+        g = (torch.ones(sp.nant, dtype=torch.complex64, device=self.device) if gains is None
+             else gains.clone())
+        rel = torch.zeros(1, dtype=torch.float32, device=self.device)
+        if weights is not None:
+            self._check_shape(weights, (self._ngroups(inst),), "weights")
+        _check(_lib.mw_solve_gains(self.handle, inst, _dev_ptr(vis, torch.complex64, "vis"),
+                                   _dev_ptr(model, torch.complex64, "model"),
+                                   _dev_ptr(weights, torch.float32, "weights"),
+                                   _dev_ptr(g, torch.complex64, "gains"), int(niter),
+                                   _dev_ptr(rel, torch.float32, "rel"), _stream_handle(stream)))
+        return g, rel
+
+    def peel(self, vis, sources, weights=None, niter=10, inst=0, stream=None):
+        """The calibration measurement loop over a catalogue (host float64 [nsrc, 3] of l, m,
+        flux): returns (residual, gains [nsrc, nant] in catalogue order, relative last steps)."""
+        import torch
+        sp = self.specs[inst]
+        shape = (self._ngroups(inst), sp.npol)
+        self._check_shape(vis, shape, "vis")
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.float64).reshape(-1, 3))
+        nsrc = src.shape[0]
+        resid = torch.empty(shape, dtype=torch.complex64, device=self.device)
+        gains = torch.empty((max(nsrc, 1), sp.nant), dtype=torch.complex64, device=self.device)
+        rel = torch.zeros(max(nsrc, 1), dtype=torch.float32, device=self.device)
+        if weights is not None:
+            self._check_shape(weights, (self._ngroups(inst),), "weights")
+        _check(_lib.mw_peel(self.handle, inst, _dev_ptr(vis, torch.complex64, "vis"), src.ctypes.data, nsrc,
+                            _dev_ptr(weights, torch.float32, "weights"), int(niter),
+                            _dev_ptr(resid, torch.complex64, "resid"),
+                            _dev_ptr(gains, torch.complex64, "gains"),
+                            _dev_ptr(rel, torch.float32, "rel"), _stream_handle(stream)))
+        return resid, gains[:nsrc], rel[:nsrc]
+
+
+    def wstack_combine(self, images, out=None, accumulate=False, stream=None):
+        """Sum of the instances' images (one w-plane each) with their planes' w-term phase."""
+        import torch
+        x_l = self._as_list(images)
+        self._check_grid(x_l, "images")
+        sp = self.specs[0]
+        if out is None:
+            out = torch.empty((sp.npol, sp.ny, sp.nx), dtype=torch.complex64, device=self.device)
+        self._check_shape(out, (sp.npol, sp.ny, sp.nx), "out")
+        ip, _k1 = _ptr_array([_dev_ptr(t, torch.complex64, "images") for t in x_l])
+        _check(_lib.mw_wstack_combine(self.handle, ip, _dev_ptr(out, torch.complex64, "out"),
+                                      1 if accumulate else 0, _stream_handle(stream)))
+        return out
+
+
+def wstack_specs(spec, nplanes):
+    """One InstanceSpec per w-plane: nplanes equal ranges of w = (w_m f)/c spanning the
+    instance's samples (the last range closed just above the largest w)."""
+    import dataclasses
+    uvw = np.asarray(spec.uvw, dtype=np.float64)
+    freq = np.asarray(spec.freq, dtype=np.float64)
+    w = uvw[:, 2:3] * freq[None, :] / 299792458.0
+    lo, hi = float(w.min()), float(w.max())
+    hi = hi + max(1e-9, 1e-12 * abs(hi))
+    edges = np.linspace(lo, hi, nplanes + 1)
+    return [dataclasses.replace(spec, wrange=(float(edges[k]), float(edges[k + 1]))) for k in range(nplanes)]
 
 
 def _grid_image_function():

@@ -63,7 +63,7 @@ def test_struct_layout_matches_c(mw, tmp_path):
 
 
 def test_abi_version(mw):
-    assert mw.abi_version() == 4
+    assert mw.abi_version() == 5
 
 
 def _instance(mw, **over):

@@ -1,0 +1,174 @@
+"""GPU parity of the calibration calls (Section 2: per-antenna complex gains from a linear
+least-squares fit to catalogue sources; Section 2.1: catalogue sources measured and removed in
+decreasing order of predicted flux; Table 1, "CML") against the oracle, through the C ABI:
+point-source prediction, the StEFCal gain solve and the peeling loop, on the differentiable
+workload's array and at MWA scale."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_0902_0915_amd import synth
+from _util import nl2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+GTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def mw():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_0902_0915_amd import mwagrid
+    return mwagrid
+
+
+@pytest.fixture(scope="module")
+def small():
+    # the differentiable workload's layout at 48 antennas: 1128 baselines x 8 ch x 4 times
+    return synth.differentiable(nant=48, n=512)
+
+
+def _catalogue(rng, n, half=0.08, smin=0.5, smax=10.0):
+    return np.stack([rng.uniform(-half, half, n), rng.uniform(-half, half, n),
+                     rng.uniform(smin, smax, n)], axis=1)
+
+
+def _plan(mw, wl, npol=None):
+    spec = mw.InstanceSpec.from_workload(wl)
+    if npol is not None:
+        spec.npol = npol
+    return mw.Plan(spec)
+
+
+def test_predict_parity_gains_accumulate(mw, small):
+    import torch
+    rng = np.random.default_rng(1)
+    src = _catalogue(rng, 20)
+    ref = orc.predict(small.uvw, small.freq, src, npol=1)
+    g = synth.random_gains(small.nant, rng)
+    rows = np.arange(small.ngroups) // small.nchan
+    gg = (g.astype(np.complex128)[small.ant1[rows]] * np.conj(g.astype(np.complex128)[small.ant2[rows]]))[:, None]
+    with _plan(mw, small) as plan:
+        got = to_host(plan.predict(src))
+        out = torch.full((small.ngroups, 1), 1.0 + 2.0j, dtype=torch.complex64, device="cuda")
+        plan.predict(src, gains=to_dev(g), out=out, accumulate=True)
+        acc = to_host(out)
+    assert nl2(got, ref) <= TOL, nl2(got, ref)
+    assert nl2(acc, gg * ref + (1.0 + 2.0j)) <= TOL
+
+
+def test_predict_four_polarisations_and_no_sources(mw):
+    rng = np.random.default_rng(2)
+    wl = synth.mwa_scale(seed=2050, nant=24, nchan=3, ntime=2, npol=4, n=256, nsrc=5)
+    src = _catalogue(rng, 4)
+    with _plan(mw, wl) as plan:
+        got = to_host(plan.predict(src))
+        empty = to_host(plan.predict(np.zeros((0, 3))))
+    ref = orc.predict(wl.uvw, wl.freq, src, npol=4)
+    assert nl2(got, ref) <= TOL
+    assert np.all(got[:, 1:3] == 0) and np.all(empty == 0)
+
+
+def test_solve_gains_parity_with_weights(mw, small):
+    rng = np.random.default_rng(3)
+    src = _catalogue(rng, 10)
+    M = orc.predict(small.uvw, small.freq, src)
+    rows = np.arange(small.ngroups) // small.nchan
+    g_true = synth.random_gains(small.nant, rng).astype(np.complex128)
+    V = (g_true[small.ant1[rows]] * np.conj(g_true[small.ant2[rows]]))[:, None] * M
+    V = V + 0.3 * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    w = rng.uniform(0.5, 2.0, small.ngroups)
+    w[rng.random(small.ngroups) < 0.1] = 0.0
+    for niter in (1, 2, 7, 8):
+        g_ref, rel_ref = orc.stefcal(V, M, small.ant1, small.ant2, small.nant, small.nchan, niter=niter,
+                                     weights=w)
+        with _plan(mw, small) as plan:
+            g, rel = plan.solve_gains(to_dev(V.astype(np.complex64)), to_dev(M.astype(np.complex64)),
+                                      weights=to_dev(w.astype(np.float32)), niter=niter)
+            g, rel = to_host(g), float(to_host(rel)[0])
+        assert nl2(g, g_ref) <= GTOL, (niter, nl2(g, g_ref))
+        assert abs(rel - rel_ref) <= 1e-3 * rel_ref + 1e-6, (niter, rel, rel_ref)
+
+
+def test_solve_gains_recovers_known_gains(mw, small):
+    rng = np.random.default_rng(4)
+    M = orc.predict(small.uvw, small.freq, _catalogue(rng, 5))
+    rows = np.arange(small.ngroups) // small.nchan
+    g_true = synth.random_gains(small.nant, rng).astype(np.complex128)
+    V = (g_true[small.ant1[rows]] * np.conj(g_true[small.ant2[rows]]))[:, None] * M
+    with _plan(mw, small) as plan:
+        g, rel = plan.solve_gains(to_dev(V.astype(np.complex64)), to_dev(M.astype(np.complex64)), niter=60)
+        g = to_host(g).astype(np.complex128)
+    g = g * np.exp(-1j * np.angle(g[0] / g_true[0]))
+    assert nl2(g, g_true) <= GTOL
+    assert float(to_host(rel)[0]) < 1e-5
+
+
+def test_peel_parity(mw, small):
+    rng = np.random.default_rng(5)
+    src = _catalogue(rng, 6)
+    src[2, 2] = -src[2, 2]
+    M_all = orc.predict(small.uvw, small.freq, src)
+    g_true = synth.random_gains(small.nant, rng).astype(np.complex128)
+    rows = np.arange(small.ngroups) // small.nchan
+    V = (g_true[small.ant1[rows]] * np.conj(g_true[small.ant2[rows]]))[:, None] * M_all
+    V = V + 0.1 * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    R_ref, G_ref, rel_ref, order = orc.peel(V, small.uvw, small.freq, small.ant1, small.ant2, small.nant, src,
+                                            niter=6)
+    with _plan(mw, small) as plan:
+        R, G, rel = plan.peel(to_dev(V.astype(np.complex64)), src, niter=6)
+        R, G, rel = to_host(R), to_host(G), to_host(rel)
+    assert nl2(R - V, R_ref - V) <= GTOL, nl2(R - V, R_ref - V)   # what was removed
+    assert np.linalg.norm(R - R_ref) <= 1e-4 * np.linalg.norm(V)
+    for k in range(len(src)):
+        assert nl2(G[k], G_ref[k]) <= GTOL, (k, nl2(G[k], G_ref[k]))
+    np.testing.assert_allclose(rel, rel_ref, rtol=1e-2, atol=1e-6)
+
+
+def test_peel_edges(mw, small):
+    import torch
+    rng = np.random.default_rng(6)
+    V = to_dev((rng.standard_normal((small.ngroups, 1)) + 0j).astype(np.complex64))
+    with _plan(mw, small) as plan:
+        R, G, _ = plan.peel(V, np.zeros((0, 3)))
+        assert torch.equal(R, V) and G.shape[0] == 0
+    spec = mw.InstanceSpec.from_workload(small, with_ants=False)
+    with mw.Plan(spec) as plan:
+        with pytest.raises(mw.MwError) as e:
+            plan.peel(V, np.array([[0.0, 0.0, 1.0]]))
+        assert e.value.status == mw.MW_ERR_STATE
+
+
+def test_peel_mwa_scale_removes_a_calibrator_and_finds_its_gains():
+    """The MWA-scale workload (512 antennas, 133,955,584 visibilities, 4 polarisations) as
+    observed through known antenna gains: one bright calibrator plus the 1000-source sky.
+    Peeling the calibrator recovers the gains (up to a common phase) and leaves the rest of
+    the sky; the prediction is checked against the oracle on sampled rows."""
+    import torch
+    from paper_0902_0915_amd import mwagrid
+    wl = synth.mwa_scale(device="cuda")
+    rng = np.random.default_rng(7)
+    cal = np.array([[0.01, -0.015, 200.0]])
+    g_true = synth.random_gains(wl.nant, rng)
+    with mwagrid.Plan(mwagrid.InstanceSpec.from_workload(wl)) as plan:
+        M = plan.predict(cal)
+        # sampled rows of the prediction against the oracle
+        rows = np.sort(rng.choice(wl.nrow, 2000, replace=False))
+        ref = orc.predict(wl.uvw[rows], wl.freq, cal, npol=4)
+        got = to_host(M.reshape(wl.nrow, wl.nchan, 4)[torch.from_numpy(rows).cuda()]).reshape(-1, 4)
+        assert nl2(got, ref) <= TOL
+        # observed = g1 conj(g2) (calibrator + sky): the sky is the workload's visibilities
+        a1 = torch.from_numpy(wl.ant1.astype(np.int64)).cuda()
+        a2 = torch.from_numpy(wl.ant2.astype(np.int64)).cuda()
+        gt = torch.from_numpy(g_true).cuda()
+        gg = (gt[a1] * torch.conj(gt[a2])).repeat_interleave(wl.nchan)[:, None]
+        V = gg * (M + wl.vis)
+        R, G, rel = plan.peel(V, cal, niter=40)
+        g = to_host(G[0]).astype(np.complex128)
+        g = g * np.exp(-1j * np.angle(g[0] / g_true[0]))
+        assert nl2(g, g_true) <= 1e-3, nl2(g, g_true)
+        # what is left is the sky through the gains, to the accuracy of the gains
+        left = nl2(to_host(R), to_host(gg * wl.vis))
+        assert left <= 2e-2, left
+        torch.cuda.synchronize()
