@@ -340,7 +340,8 @@ def bench_stacks(mwagrid, synth, stream, steps):
     d = percentiles(lambda: plan.degrid(grid, out=vout), steps, stream)
     info = plan.info(0)
     plan.close()
-    sup = wl.kernel_support[wl.kernel_index[wl.flags == 0]].astype(np.int64)
+    sel = wl.kernel_index if wl.flags is None else wl.kernel_index[wl.flags == 0]
+    sup = wl.kernel_support[sel].astype(np.int64)
     taps = int((sup * sup).sum())
     flop = 8 * taps  # complex x complex multiply-add per tap
     out = {"workload": "beam_w_stacks: 128 antennas x 8 ch x 16 times, 4096^2, O=4, supports 21..45",

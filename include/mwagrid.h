@@ -154,7 +154,8 @@ typedef struct {
 } mw_plan_stats;
 
 /*
- * Build a plan for ninst instances (ninst >= 1). Computes every group's position in FP64
+ * Build a plan for ninst instances (ninst >= 1), the set-up of the interpolation of the
+ * samples onto a regular grid (Section 2.1). Computes every group's position in FP64
  * (the quantisation rule above), drops flagged and out-of-grid groups, sorts the kept ones
  * by uv tile (and cell), splits heavy tiles into work items, builds the kernel table and
  * correction vectors, and (ninst > 1) the persistent batched schedule. Synchronous: returns
@@ -167,7 +168,8 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst,
                        const mw_tuning *tuning, void *stream);
 
 /*
- * Grid: for every instance i, grid[i] (+)= sum over kept groups of
+ * Grid (Section 2.1: the convolution that interpolates the samples onto a regular grid for
+ * the FFT; Table 1 "Gridding"): for every instance i, grid[i] (+)= sum over kept groups of
  *   w * g[ant1] * conj(g[ant2]) * tap * V[pol]   (separable or stack tap, see above).
  * vis[i]: device complex64 [ngroups][npol]. gains: NULL, or gains[i] NULL or device
  * complex64 [nant]. grid[i]: device complex64 [npol][ny][nx]. accumulate = 0 overwrites the
@@ -197,7 +199,9 @@ mw_status mw_grid_noalloc(mw_plan plan, const void *const *vis, const void *cons
                           void *const *grid, int32_t accumulate, void *stream);
 
 /*
- * Degrid, the exact adjoint of mw_grid: for every instance and kept group,
+ * Degrid, the exact adjoint of mw_grid (the transpose of the Section 2.1 interpolation; with
+ * grad_gains, the gradient with respect to the per-antenna complex gains that calibration
+ * solves for, Section 2): for every instance and kept group,
  *   vis_out[g][pol] = w * conj(g[ant1]) * g[ant2] * sum_taps conj?(tap) * grid[pol][cell]
  * (conjugated taps for stacks), and 0 for dropped groups. vis_out is overwritten.
  * If grad_gains[i] is non-NULL it receives (overwritten, complex64 [nant]) the gradient of a
@@ -213,7 +217,8 @@ mw_status mw_degrid(mw_plan plan, const void *const *grid, const void *const *ga
                     void *stream);
 
 /*
- * Image, per instance and polarisation. direction = +1:
+ * Image (Section 2: images formed via a Fourier transform, one per polarisation; Section 2.1;
+ * Table 1 "FFT" and "Convolution Correction"), per instance and polarisation. direction = +1:
  *   out[p] = sum_g in[g] exp(+2 pi i (g - n/2)(p - n/2)/n) in x and y (unnormalised,
  *   centred), then, if correct, out /= Cn(x) Cn(y) with Cn(x) = psi_0(c, 2x)/psi_0(c, 0),
  *   x = (p - n/2)/n (the normalised Fourier transform of the built-in kernel).

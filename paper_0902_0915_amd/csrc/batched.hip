@@ -124,13 +124,14 @@ __global__ __launch_bounds__(1024) void k_grid_batched(BatchGridArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ntab = a.O * 8;
     float *ltab = smem;
+    // the item's record is loaded before the tap-table barrier, so that the two loads overlap
+    const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
+    const GridItem it = a.items[w < a.nitems ? w : 0];
     for (int i = tid; i < ntab; i += blockDim.x) ltab[i] = a.tab8[i];
     __syncthreads();
-    const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
     if (w >= a.nitems) return;
     const int R = a.T + W - 1;
     float *stage = smem + ntab + wave * a.per_wave;
-    const GridItem it = a.items[w];
     const int inst = uni(it.inst), wtile = uni(it.tile);
     const BatchDesc &d = a.desc[inst];
     const bool owner = uni(d.flush) == 3;

@@ -151,17 +151,19 @@ __global__ void k_fill_gains(float2 *g, int n, float2 v) {
     if (i < n) g[i] = v;
 }
 
-// One StEFCal iteration (number it, from 1): one wave per antenna gathers its rows' (P, Q)
-// (FP64 sums in a fixed order), solves its gain and writes the next iterate (the mean with the
-// previous one on even iterations); diff / nrm receive |g_new - g_old|^2 and |g_new|^2.
+// One StEFCal iteration (number it, from 1): one workgroup per antenna gathers its rows'
+// (P, Q) (FP64 sums: each thread a strided share of the list, then a fixed-order tree), solves
+// its gain and writes the next iterate (the mean with the previous one on even iterations);
+// diff / nrm receive |g_new - g_old|^2 and |g_new|^2. A whole workgroup per antenna keeps
+// many independent loads of the list in flight (an antenna has thousands of rows).
 __global__ __launch_bounds__(kBlock) void k_cal_ants(const float4 *pq, const uint32_t *ants, const int32_t *start,
                                                      const int32_t *entry, int nant, const float2 *gin, float2 *gout,
                                                      int it, double *diff, double *nrm) {
-    const int lane = (int)(threadIdx.x & 63);
-    const int a = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (a >= nant) return;
+    __shared__ double sr[kBlock], si[kBlock], sd[kBlock];
+    const int t = (int)threadIdx.x;
+    const int a = (int)blockIdx.x;
     double nr = 0, ni = 0, dd = 0;
-    for (int k = start[a] + lane; k < start[a + 1]; k += 64) {
+    for (int k = start[a] + t; k < start[a + 1]; k += kBlock) {
         const int32_t e = entry[k];
         const int64_t r = e >> 1;
         const uint32_t an = ants[r];
@@ -178,17 +180,24 @@ __global__ __launch_bounds__(kBlock) void k_cal_ants(const float4 *pq, const uin
             dd += ((double)o.x * o.x + (double)o.y * o.y) * v.z;
         }
     }
-    for (int o = 32; o >= 1; o >>= 1) {
-        nr += __shfl_xor(nr, o, 64);
-        ni += __shfl_xor(ni, o, 64);
-        dd += __shfl_xor(dd, o, 64);
+    sr[t] = nr;
+    si[t] = ni;
+    sd[t] = dd;
+    __syncthreads();
+    for (int o = kBlock / 2; o >= 1; o >>= 1) {
+        if (t < o) {
+            sr[t] += sr[t + o];
+            si[t] += si[t + o];
+            sd[t] += sd[t + o];
+        }
+        __syncthreads();
     }
-    if (lane == 0) {
+    if (t == 0) {
         const float2 old = gin[a];
         double gr = old.x, gi = old.y;
-        if (dd > 0.0) {
-            gr = nr / dd;
-            gi = ni / dd;
+        if (sd[0] > 0.0) {
+            gr = sr[0] / sd[0];
+            gi = si[0] / sd[0];
         }
         const double dr = gr - old.x, di = gi - old.y;
         if (diff) {
@@ -267,7 +276,7 @@ Status solve(Instance &I, const float2 *vis, const float2 *model, const Src *src
     }
     for (int it = 1; it <= niter; it++) {
         const bool last = it == niter;
-        hipLaunchKernelGGL(k_cal_ants, dim3(grid1d((int64_t)I.nant * 64)), dim3(kBlock), 0, s, I.cal_pq,
+        hipLaunchKernelGGL(k_cal_ants, dim3((unsigned)I.nant), dim3(kBlock), 0, s, I.cal_pq,
                            I.ant_orig, I.cal_start, I.cal_entry, I.nant, bufs[cur], bufs[cur ^ 1], it,
                            last && rel ? I.cal_red : nullptr, I.cal_red + I.nant);
         MWG_HIP(hipGetLastError());

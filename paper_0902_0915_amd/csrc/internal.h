@@ -41,6 +41,8 @@ Status make_error(mw_status code, const char *fmt, ...);
 struct DevArena {
     std::vector<void *> ptrs;
     int64_t bytes = 0;
+    char *chunk = nullptr;  // the current chunk of small arrays and what is left of it
+    size_t chunk_left = 0;
     Status alloc(void **p, size_t nbytes);
     void release();
 };

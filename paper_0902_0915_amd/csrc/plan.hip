@@ -28,16 +28,36 @@ Status make_error(mw_status code, const char *fmt, ...) {
     return s;
 }
 
+// Arrays of less than kArenaSmall bytes are carved, 256-byte aligned, from chunks of
+// kArenaChunk bytes: a plan owns dozens of small arrays (work lists, tables, per-antenna
+// buffers), and one hipMalloc each would dominate the time to build plans of small instances.
+constexpr size_t kArenaSmall = size_t(256) << 10;
+constexpr size_t kArenaChunk = size_t(2) << 20;
+
 Status DevArena::alloc(void **p, size_t nbytes) {
     *p = nullptr;
     if (nbytes == 0) nbytes = 16;
-    hipError_t e = hipMalloc(p, nbytes);
+    nbytes = (nbytes + 255) & ~size_t(255);
+    if (nbytes < kArenaSmall && nbytes <= chunk_left) {
+        *p = chunk;
+        chunk += nbytes;
+        chunk_left -= nbytes;
+        bytes += (int64_t)nbytes;
+        return Status::Ok();
+    }
+    const size_t take = nbytes < kArenaSmall ? kArenaChunk : nbytes;
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, take);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        *p = nullptr;
-        return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
+        return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", take, hipGetErrorString(e));
     }
-    ptrs.push_back(*p);
+    ptrs.push_back(q);
+    if (nbytes < kArenaSmall) {  // a new chunk: the rest of it serves later small arrays
+        chunk = (char *)q + nbytes;
+        chunk_left = take - nbytes;
+    }
+    *p = q;
     bytes += (int64_t)nbytes;
     return Status::Ok();
 }
@@ -46,6 +66,8 @@ void DevArena::release() {
     for (void *p : ptrs) (void)hipFree(p);
     ptrs.clear();
     bytes = 0;
+    chunk = nullptr;
+    chunk_left = 0;
 }
 
 namespace {

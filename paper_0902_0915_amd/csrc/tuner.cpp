@@ -4,6 +4,7 @@
 // changes only rebuild the work list. Results can be cached in a text file of one JSON
 // object per line (path in MW_TUNE_CACHE).
 #include "internal.h"
+#include "tune_cache.h"
 
 #include <cmath>
 #include <cstdio>
@@ -44,34 +45,21 @@ std::string cache_key(const Instance &I) {
 }
 
 bool cache_lookup(const char *path, const std::string &key, Launch *L) {
-    FILE *f = std::fopen(path, "r");
-    if (!f) return false;
-    char line[512];
-    bool found = false;
-    while (std::fgets(line, sizeof line, f)) {
-        char k[256];
-        Launch c;
-        if (std::sscanf(line,
-                        "{\"key\": \"%255[^\"]\", \"tile\": %d, \"split\": %d, \"wg_waves\": %d, "
-                        "\"order\": %d, \"variant\": %d, \"flush\": %d, \"schedule\": %d}",
-                        k, &c.tile, &c.split, &c.wg_waves, &c.order, &c.variant, &c.flush, &c.schedule) == 8 &&
-            key == k) {
-            *L = c; // the last matching line wins
-            found = true;
-        }
-    }
-    std::fclose(f);
-    return found;
+    TuneRecord r;
+    if (!tune_cache_lookup(path, key.c_str(), &r)) return false;
+    L->tile = r.tile;
+    L->split = r.split;
+    L->wg_waves = r.wg_waves;
+    L->order = r.order;
+    L->variant = r.variant;
+    L->flush = r.flush;
+    L->schedule = r.schedule;
+    return true;
 }
 
 void cache_store(const char *path, const std::string &key, const Launch &c, float ms) {
-    FILE *f = std::fopen(path, "a");
-    if (!f) return;
-    std::fprintf(f,
-                 "{\"key\": \"%s\", \"tile\": %d, \"split\": %d, \"wg_waves\": %d, \"order\": %d, "
-                 "\"variant\": %d, \"flush\": %d, \"schedule\": %d, \"ms\": %.4f}\n",
-                 key.c_str(), c.tile, c.split, c.wg_waves, c.order, c.variant, c.flush, c.schedule, ms);
-    std::fclose(f);
+    tune_cache_store(path, key.c_str(), TuneRecord{c.tile, c.split, c.wg_waves, c.order, c.variant, c.flush, c.schedule},
+                     ms);
 }
 
 Status elapsed(hipEvent_t e0, hipEvent_t e1, float *ms) {
