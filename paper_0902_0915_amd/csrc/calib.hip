@@ -56,14 +56,14 @@ struct Src {
 // Model visibilities of nsrc point sources (sources in global memory, read through L1), times
 // g[a1] conj(g[a2]) when gains are given; written or added to out [ng][npol]. Cross
 // polarisations (1, 2 of 4) of an unpolarised source are zero. One thread per group.
-__global__ __launch_bounds__(kBlock) void k_predict(const double *uvw, const double *freq, int64_t ng, int nchan,
+__global__ __launch_bounds__(kBlock) void k_predict(const double *uvw, const double *kf, int64_t ng, int nchan,
                                                     int npol, const Src *src, int nsrc, const float2 *gains,
                                                     const uint32_t *ants, float2 *out, int accumulate) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ng) return;
-    const int64_t r = g / nchan;
-    const int c = (int)(g - r * nchan);
-    const double k = freq[c] / kC;  // turns per metre
+    const uint32_t r = (uint32_t)g / (uint32_t)nchan;  // ngroups < 2^31
+    const int c = (int)((uint32_t)g - r * (uint32_t)nchan);
+    const double k = kf[c];  // turns per metre, f / c
     const double u = uvw[3 * r], v = uvw[3 * r + 1], w = uvw[3 * r + 2];
     float sr = 0.f, si = 0.f;
     for (int j = 0; j < nsrc; j++) {
@@ -96,54 +96,55 @@ __global__ __launch_bounds__(kBlock) void k_predict(const double *uvw, const dou
 
 // Per-row (P, Q) against a model array or one predicted source. A segment of L lanes (a power
 // of two <= 64) takes one row: lanes stride over its nchan * npol samples, then the segment
-// sums its values by butterfly shuffles (fixed order).
+// sums its values by butterfly shuffles (fixed order). Each wave takes 64 / L rows at a time
+// and strides over the rows, so that a wave does a useful amount of work.
 template <bool FROM_SOURCE>
 __global__ __launch_bounds__(kBlock) void k_cal_rows(const float2 *vis, const float2 *model, const double *uvw,
-                                                     const double *freq, const Src *src, const float *weights,
+                                                     const double *kf, const Src *src, const float *weights,
                                                      int64_t nrow, int nchan, int npol, int L, float4 *pq) {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int seg = lane / L, sl = lane % L;
-    const int64_t r = wave * (64 / L) + seg;
-    const bool live = r < nrow;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int spw = 64 / L, seg = lane / L, sl = lane % L;
+    const int pshift = npol == 4 ? 2 : (npol == 2 ? 1 : 0);
     const int ne = nchan * npol;
-    float pr = 0.f, pi = 0.f, q = 0.f;
-    if (live) {
-        double u = 0, v = 0, w = 0;
-        Src s{};
-        if constexpr (FROM_SOURCE) {
-            u = uvw[3 * r];
-            v = uvw[3 * r + 1];
-            w = uvw[3 * r + 2];
-            s = *src;
-        }
-        for (int e = sl; e < ne; e += L) {
-            const int c = e / npol, p = e - c * npol;
-            const int64_t g = r * nchan + c;
-            const float wt = weights ? weights[g] : 1.0f;
-            if (wt == 0.0f) continue;
-            float2 M;
-            if constexpr (FROM_SOURCE) {
-                const bool cross = npol == 4 && (p == 1 || p == 2);
-                if (cross) continue;
-                const float2 ph = turn_phasor((u * s.l + v * s.m + w * s.n1) * (freq[c] / kC));
-                M = make_float2((float)s.flux * ph.x, (float)s.flux * ph.y);
-            } else {
-                M = model[g * npol + p];
+    Src s{};
+    if constexpr (FROM_SOURCE) s = *src;
+    for (int64_t r0 = wave * spw; r0 < nrow; r0 += nwave * spw) {
+        const int64_t r = r0 + seg;
+        const bool live = r < nrow;
+        float pr = 0.f, pi = 0.f, q = 0.f;
+        if (live) {
+            double path = 0.0;
+            if constexpr (FROM_SOURCE) path = uvw[3 * r] * s.l + uvw[3 * r + 1] * s.m + uvw[3 * r + 2] * s.n1;
+            for (int e = sl; e < ne; e += L) {
+                const int c = e >> pshift, p = e & (npol - 1);
+                const int64_t g = r * nchan + c;
+                const float wt = weights ? weights[g] : 1.0f;
+                if (wt == 0.0f) continue;
+                float2 M;
+                if constexpr (FROM_SOURCE) {
+                    const bool cross = npol == 4 && (p == 1 || p == 2);
+                    if (cross) continue;
+                    const float2 ph = turn_phasor(path * kf[c]);
+                    M = make_float2((float)s.flux * ph.x, (float)s.flux * ph.y);
+                } else {
+                    M = model[g * npol + p];
+                }
+                const float2 V = vis[g * npol + p];
+                // conj(M) V and |M|^2, weighted
+                pr += wt * (M.x * V.x + M.y * V.y);
+                pi += wt * (M.x * V.y - M.y * V.x);
+                q += wt * (M.x * M.x + M.y * M.y);
             }
-            const float2 V = vis[g * npol + p];
-            // conj(M) V and |M|^2, weighted
-            pr += wt * (M.x * V.x + M.y * V.y);
-            pi += wt * (M.x * V.y - M.y * V.x);
-            q += wt * (M.x * M.x + M.y * M.y);
         }
+        for (int o = L / 2; o >= 1; o >>= 1) {
+            pr += __shfl_xor(pr, o, 64);
+            pi += __shfl_xor(pi, o, 64);
+            q += __shfl_xor(q, o, 64);
+        }
+        if (live && sl == 0) pq[r] = make_float4(pr, pi, q, 0.f);
     }
-    for (int o = L / 2; o >= 1; o >>= 1) {
-        pr += __shfl_xor(pr, o, 64);
-        pi += __shfl_xor(pi, o, 64);
-        q += __shfl_xor(q, o, 64);
-    }
-    if (live && sl == 0) pq[r] = make_float4(pr, pi, q, 0.f);
 }
 
 __global__ void k_fill_gains(float2 *g, int n, float2 v) {
@@ -156,29 +157,23 @@ __global__ void k_fill_gains(float2 *g, int n, float2 v) {
 // its gain and writes the next iterate (the mean with the previous one on even iterations);
 // diff / nrm receive |g_new - g_old|^2 and |g_new|^2. A whole workgroup per antenna keeps
 // many independent loads of the list in flight (an antenna has thousands of rows).
-__global__ __launch_bounds__(kBlock) void k_cal_ants(const float4 *pq, const uint32_t *ants, const int32_t *start,
+__global__ __launch_bounds__(kBlock) void k_cal_ants(const float4 *pq, const int32_t *partner, const int32_t *start,
                                                      const int32_t *entry, int nant, const float2 *gin, float2 *gout,
                                                      int it, double *diff, double *nrm) {
     __shared__ double sr[kBlock], si[kBlock], sd[kBlock];
     const int t = (int)threadIdx.x;
     const int a = (int)blockIdx.x;
     double nr = 0, ni = 0, dd = 0;
+#pragma unroll 4
     for (int k = start[a] + t; k < start[a + 1]; k += kBlock) {
         const int32_t e = entry[k];
-        const int64_t r = e >> 1;
-        const uint32_t an = ants[r];
-        const float4 v = pq[r];
-        if ((e & 1) == 0) {  // a1(r) = a: g[a2] P
-            const float2 o = gin[an >> 16];
-            nr += (double)o.x * v.x - (double)o.y * v.y;
-            ni += (double)o.x * v.y + (double)o.y * v.x;
-            dd += ((double)o.x * o.x + (double)o.y * o.y) * v.z;
-        } else {             // a2(r) = a: g[a1] conj(P)
-            const float2 o = gin[an & 0xFFFFu];
-            nr += (double)o.x * v.x + (double)o.y * v.y;
-            ni += (double)o.y * v.x - (double)o.x * v.y;
-            dd += ((double)o.x * o.x + (double)o.y * o.y) * v.z;
-        }
+        const float4 v = pq[e >> 1];
+        const float2 o = gin[partner[k]];
+        // a1(r) = a: g[a2] P; a2(r) = a: g[a1] conj(P)
+        const double pim = (e & 1) ? -(double)v.y : (double)v.y;
+        nr += (double)o.x * v.x - (double)o.y * pim;
+        ni += (double)o.x * pim + (double)o.y * v.x;
+        dd += ((double)o.x * o.x + (double)o.y * o.y) * v.z;
     }
     sr[t] = nr;
     si[t] = ni;
@@ -258,13 +253,15 @@ Status solve(Instance &I, const float2 *vis, const float2 *model, const Src *src
              int niter, float *rel, hipStream_t s) {
     const int L = lanes_per_row(I.nchan * I.npol);
     const int64_t waves = (I.nrow + (64 / L) - 1) / (64 / L);
+    // about 16 rounds of rows per wave, at most 2048 workgroups
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (waves + 63) / 64));
     if (I.nrow > 0) {
         if (src)
-            hipLaunchKernelGGL(k_cal_rows<true>, dim3(grid1d(waves * 64)), dim3(kBlock), 0, s, vis, model, I.uvw_d,
-                               I.freq_d, src, weights, I.nrow, I.nchan, I.npol, L, I.cal_pq);
+            hipLaunchKernelGGL(k_cal_rows<true>, dim3(blocks), dim3(kBlock), 0, s, vis, model, I.uvw_d, I.kf_d, src,
+                               weights, I.nrow, I.nchan, I.npol, L, I.cal_pq);
         else
-            hipLaunchKernelGGL(k_cal_rows<false>, dim3(grid1d(waves * 64)), dim3(kBlock), 0, s, vis, model, I.uvw_d,
-                               I.freq_d, src, weights, I.nrow, I.nchan, I.npol, L, I.cal_pq);
+            hipLaunchKernelGGL(k_cal_rows<false>, dim3(blocks), dim3(kBlock), 0, s, vis, model, I.uvw_d, I.kf_d, src,
+                               weights, I.nrow, I.nchan, I.npol, L, I.cal_pq);
         MWG_HIP(hipGetLastError());
     }
     // ping-pong between g and the plan's second gain buffer, ending in g
@@ -277,7 +274,7 @@ Status solve(Instance &I, const float2 *vis, const float2 *model, const Src *src
     for (int it = 1; it <= niter; it++) {
         const bool last = it == niter;
         hipLaunchKernelGGL(k_cal_ants, dim3((unsigned)I.nant), dim3(kBlock), 0, s, I.cal_pq,
-                           I.ant_orig, I.cal_start, I.cal_entry, I.nant, bufs[cur], bufs[cur ^ 1], it,
+                           I.cal_partner, I.cal_start, I.cal_entry, I.nant, bufs[cur], bufs[cur ^ 1], it,
                            last && rel ? I.cal_red : nullptr, I.cal_red + I.nant);
         MWG_HIP(hipGetLastError());
         cur ^= 1;
@@ -303,9 +300,17 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     I.uvw_d = (double *)p;
     if (I.nrow > 0)
         MWG_HIP(hipMemcpyAsync(I.uvw_d, uvw_dev, sizeof(double) * 3 * (size_t)I.nrow, hipMemcpyDeviceToDevice, s));
-    MWG_TRY(I.arena.alloc(&p, sizeof(double) * (size_t)I.nchan));
-    I.freq_d = (double *)p;
-    MWG_HIP(hipMemcpyAsync(I.freq_d, freq_dev, sizeof(double) * (size_t)I.nchan, hipMemcpyDeviceToDevice, s));
+    {
+        // turns per metre of every channel, f / c, formed on the host in FP64
+        std::vector<double> kf((size_t)I.nchan);
+        MWG_HIP(hipMemcpyAsync(kf.data(), freq_dev, sizeof(double) * (size_t)I.nchan, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipStreamSynchronize(s));
+        for (double &f : kf) f = f / kC;
+        MWG_TRY(I.arena.alloc(&p, sizeof(double) * (size_t)I.nchan));
+        I.kf_d = (double *)p;
+        MWG_HIP(hipMemcpyAsync(I.kf_d, kf.data(), sizeof(double) * (size_t)I.nchan, hipMemcpyHostToDevice, s));
+        MWG_HIP(hipStreamSynchronize(s));
+    }
     if (!I.has_ants) return Status::Ok();
     std::vector<int32_t> h1((size_t)I.nrow), h2((size_t)I.nrow);
     if (I.nrow > 0) {
@@ -314,7 +319,7 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     }
     MWG_HIP(hipStreamSynchronize(s));
     // rows of each antenna: entry = row << 1 | (0: as ant1, 1: as ant2), rows ascending
-    std::vector<int32_t> start((size_t)I.nant + 1, 0), entry(2 * (size_t)I.nrow);
+    std::vector<int32_t> start((size_t)I.nant + 1, 0), entry(2 * (size_t)I.nrow), partner(2 * (size_t)I.nrow);
     for (int64_t r = 0; r < I.nrow; r++) {
         start[h1[r] + 1]++;
         start[h2[r] + 1]++;
@@ -323,7 +328,9 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     {
         std::vector<int32_t> fill(start.begin(), start.end() - 1);
         for (int64_t r = 0; r < I.nrow; r++) {
+            partner[fill[h1[r]]] = h2[r];
             entry[fill[h1[r]]++] = (int32_t)(r << 1);
+            partner[fill[h2[r]]] = h1[r];
             entry[fill[h2[r]]++] = (int32_t)(r << 1 | 1);
         }
     }
@@ -332,6 +339,8 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     I.cal_start = (int32_t *)p;
     MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(entry.size(), 1)));
     I.cal_entry = (int32_t *)p;
+    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(partner.size(), 1)));
+    I.cal_partner = (int32_t *)p;
     MWG_TRY(I.arena.alloc(&p, sizeof(float4) * (size_t)std::max<int64_t>(I.nrow, 1)));
     I.cal_pq = (float4 *)p;
     MWG_TRY(I.arena.alloc(&p, sizeof(float2) * (size_t)I.nant));
@@ -339,8 +348,10 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     MWG_TRY(I.arena.alloc(&p, sizeof(double) * 2 * (size_t)I.nant));
     I.cal_red = (double *)p;
     MWG_HIP(hipMemcpyAsync(I.cal_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice, s));
-    if (!entry.empty())
+    if (!entry.empty()) {
         MWG_HIP(hipMemcpyAsync(I.cal_entry, entry.data(), 4 * entry.size(), hipMemcpyHostToDevice, s));
+        MWG_HIP(hipMemcpyAsync(I.cal_partner, partner.data(), 4 * partner.size(), hipMemcpyHostToDevice, s));
+    }
     MWG_HIP(hipStreamSynchronize(s));
     return Status::Ok();
 }
@@ -352,7 +363,7 @@ Status launch_predict(Instance &I, const double *sources, int nsrc, const float2
     if (gains && !I.has_ants) return make_error(MW_ERR_STATE, "gains given for an instance planned without antennas");
     // the source table as (l, m, n - 1, S) in the plan's device buffer
     MWG_TRY(stage_sources(I, sources, nsrc, false, s));
-    hipLaunchKernelGGL(k_predict, dim3(grid1d(I.ngroups)), dim3(kBlock), 0, s, I.uvw_d, I.freq_d, I.ngroups, I.nchan,
+    hipLaunchKernelGGL(k_predict, dim3(grid1d(I.ngroups)), dim3(kBlock), 0, s, I.uvw_d, I.kf_d, I.ngroups, I.nchan,
                        I.npol, (const Src *)I.src_d, nsrc, gains, I.ant_orig, out, accumulate);
     MWG_HIP(hipGetLastError());
     return Status::Ok();
@@ -385,7 +396,7 @@ Status launch_peel(Instance &I, const float2 *vis, const double *sources_host, i
         hipLaunchKernelGGL(k_fill_gains, dim3(grid1d(I.nant)), dim3(kBlock), 0, s, gk, I.nant, make_float2(1.f, 0.f));
         MWG_HIP(hipGetLastError());
         MWG_TRY(solve(I, resid, nullptr, table + k, weights, gk, niter, rel ? rel + k : nullptr, s));
-        hipLaunchKernelGGL(k_predict, dim3(grid1d(I.ngroups)), dim3(kBlock), 0, s, I.uvw_d, I.freq_d, I.ngroups,
+        hipLaunchKernelGGL(k_predict, dim3(grid1d(I.ngroups)), dim3(kBlock), 0, s, I.uvw_d, I.kf_d, I.ngroups,
                            I.nchan, I.npol, table + nsrc + k, 1, (const float2 *)gk, I.ant_orig, resid, 1);
         MWG_HIP(hipGetLastError());
     }

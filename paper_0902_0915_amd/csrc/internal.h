@@ -156,9 +156,10 @@ struct Instance {
     double wlo = 0, whi = 0;
     // prediction and calibration (calib.hip)
     double *uvw_d = nullptr;      // [nrow][3] metres
-    double *freq_d = nullptr;     // [nchan] Hz
+    double *kf_d = nullptr;       // [nchan] f / c, turns per metre
     int32_t *cal_start = nullptr; // [nant + 1] CSR of each antenna's rows
     int32_t *cal_entry = nullptr; // [2 nrow] row << 1 | (0: the row's ant1, 1: its ant2)
+    int32_t *cal_partner = nullptr; // [2 nrow] the row's other antenna
     float4 *cal_pq = nullptr;     // [nrow] per-row sums (Re P, Im P, Q, 0)
     float2 *cal_g = nullptr;      // [nant] second gain buffer of the iteration
     double *cal_red = nullptr;    // [2 nant] per-antenna |step|^2 and |g|^2 of the last iteration
