@@ -169,6 +169,7 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
             if (!s.ok()) return fail(s);
         }
         hipStream_t st = (hipStream_t)stream;
+        mwg::TmpScope scratch(st);  // the build's temporaries, freed after the last sync below
         mwg::Plan *P = new mwg::Plan();
         if (hipGetDevice(&P->device) != hipSuccess) {
             delete P;

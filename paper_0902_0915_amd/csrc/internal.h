@@ -47,6 +47,40 @@ struct DevArena {
     void release();
 };
 
+// Temporary device memory of plan construction (sort keys, scan workspaces, counters).
+// Inside a TmpScope, temporaries on the scope's stream are carved last-in first-out from
+// blocks that the scope owns and frees when it ends, so a plan of many small instances does
+// not pay a hipMalloc/hipFree pair per temporary. Memory a temporary gives back may be handed
+// out again while kernels that read it are still queued: the next user is queued behind them
+// on the same stream. Outside a scope, or on another stream, a temporary is its own hipMalloc
+// and its destructor waits for the device (hipFree does).
+struct TmpPool;
+struct DevTmp {
+    void *p = nullptr;
+    DevTmp() = default;
+    DevTmp(const DevTmp &) = delete;
+    DevTmp &operator=(const DevTmp &) = delete;
+    ~DevTmp() { release(); }
+    Status alloc(size_t nbytes, hipStream_t s);
+    void release();
+    bool pooled() const { return pool != nullptr; }
+    template <class T> T *as() const { return (T *)p; }
+
+  private:
+    TmpPool *pool = nullptr;
+};
+
+class TmpScope {
+  public:
+    explicit TmpScope(hipStream_t s);
+    ~TmpScope();
+    TmpScope(const TmpScope &) = delete;
+    TmpScope &operator=(const TmpScope &) = delete;
+
+  private:
+    TmpPool *own = nullptr;  // null when an enclosing scope is already active on this thread
+};
+
 // Smallest r with 2^r >= v (the exponent of a power-of-two tile size).
 inline int ilog2(int v) {
     int r = 0;

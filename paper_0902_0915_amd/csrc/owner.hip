@@ -44,21 +44,7 @@ int bitlen(uint64_t v) {
     return r;
 }
 
-struct Tmp {
-    void *p = nullptr;
-    ~Tmp() {
-        if (p) (void)hipFree(p);
-    }
-    Status alloc(size_t n) {
-        if (hipMalloc(&p, n ? n : 16) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed", n);
-        }
-        return Status::Ok();
-    }
-    template <class T> T *as() { return (T *)p; }
-};
+using Tmp = DevTmp;
 
 // Output tiles [x0, x1] x [y0, y1] that the footprint of sorted group p reaches.
 __device__ inline void reach(uint32_t p, int h, int lgT, int &x0, int &x1, int &y0, int &y1) {
@@ -148,7 +134,7 @@ Status build_owner_schedule(Instance &I, int64_t cap, bool *built, hipStream_t s
     uint32_t *sk = nullptr, *sv = nullptr;
     if (nk > 0) {
         Tmp counts;
-        MWG_TRY(counts.alloc(4 * (size_t)(nk + 1)));
+        MWG_TRY(counts.alloc(4 * (size_t)(nk + 1), s));
         MWG_TRY(launch_fill_u32(counts.as<uint32_t>() + nk, 1, 0, s));
         hipLaunchKernelGGL(k_owner_count, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.spos, nk, h, lgT,
                            counts.as<uint32_t>());
@@ -158,18 +144,18 @@ Status build_owner_schedule(Instance &I, int64_t cap, bool *built, hipStream_t s
         MWG_HIP(hipMemcpyAsync(&np, counts.as<uint32_t>() + nk, 4, hipMemcpyDeviceToHost, s));
         MWG_HIP(hipStreamSynchronize(s));
         npairs = np;
-        MWG_TRY(keys.alloc(4 * (size_t)npairs));
-        MWG_TRY(keys2.alloc(4 * (size_t)npairs));
-        MWG_TRY(vals.alloc(4 * (size_t)npairs));
-        MWG_TRY(vals2.alloc(4 * (size_t)npairs));
-        MWG_TRY(vinit.alloc(4 * (size_t)npairs));
+        MWG_TRY(keys.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(keys2.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(vals.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(vals2.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(vinit.alloc(4 * (size_t)npairs, s));
         hipLaunchKernelGGL(k_owner_emit, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.spos, nk, h, lgT, ntx,
                            counts.as<uint32_t>(), keys.as<uint32_t>(), vinit.as<uint32_t>());
         MWG_HIP(hipGetLastError());
         MWG_TRY(sort_pairs(keys.as<uint32_t>(), keys2.as<uint32_t>(), vinit.as<uint32_t>(), vals.as<uint32_t>(),
                            vals2.as<uint32_t>(), npairs, std::max(1, bitlen((uint64_t)ntiles)), &sk, &sv, s));
-        MWG_TRY(tstart.alloc(4 * (size_t)ntiles));
-        MWG_TRY(tend.alloc(4 * (size_t)ntiles));
+        MWG_TRY(tstart.alloc(4 * (size_t)ntiles, s));
+        MWG_TRY(tend.alloc(4 * (size_t)ntiles, s));
         MWG_TRY(launch_fill_u32(tstart.as<uint32_t>(), ntiles, 0, s));
         MWG_TRY(launch_fill_u32(tend.as<uint32_t>(), ntiles, 0, s));
         hipLaunchKernelGGL(k_owner_bounds, dim3(grid1d(npairs)), dim3(kBlock), 0, s, sk, npairs, tstart.as<int32_t>(),

@@ -70,27 +70,113 @@ void DevArena::release() {
     chunk_left = 0;
 }
 
+// Blocks of the temporary pool grow geometrically from kTmpBlock bytes; a block, once
+// allocated, lives until its scope ends. Allocations form a stack: a record is popped when it
+// and every record above it have been given back, and the top of its block falls back to it.
+constexpr size_t kTmpBlock = size_t(16) << 20;
+
+struct TmpPool {
+    struct Block {
+        char *base;
+        size_t size, top;
+    };
+    struct Rec {
+        void *p;
+        int block;
+        size_t off;
+        bool freed;
+    };
+    hipStream_t stream = nullptr;
+    std::vector<Block> blocks;
+    std::vector<Rec> stack;
+
+    Status take(size_t nbytes, void **out) {
+        nbytes = (nbytes + 255) & ~size_t(255);
+        int b = stack.empty() ? 0 : stack.back().block;  // blocks after b are empty
+        while (b < (int)blocks.size() && blocks[b].size - blocks[b].top < nbytes) b++;
+        if (b == (int)blocks.size()) {
+            size_t want = kTmpBlock;
+            for (const Block &k : blocks) want = std::max(want, 2 * k.size);
+            want = std::max(want, nbytes);
+            void *q = nullptr;
+            hipError_t e = hipMalloc(&q, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+            }
+            blocks.push_back({(char *)q, want, 0});
+        }
+        Block &k = blocks[b];
+        *out = k.base + k.top;
+        stack.push_back({*out, b, k.top, false});
+        k.top += nbytes;
+        return Status::Ok();
+    }
+    void give_back(void *p) {
+        for (size_t i = stack.size(); i-- > 0;)
+            if (stack[i].p == p && !stack[i].freed) {
+                stack[i].freed = true;
+                break;
+            }
+        while (!stack.empty() && stack.back().freed) {
+            blocks[stack.back().block].top = stack.back().off;
+            stack.pop_back();
+        }
+    }
+};
+
+namespace {
+thread_local TmpPool *t_tmp_pool = nullptr;
+}
+
+Status DevTmp::alloc(size_t nbytes, hipStream_t s) {
+    release();
+    if (nbytes == 0) nbytes = 16;
+    if (t_tmp_pool && t_tmp_pool->stream == s) {
+        MWG_TRY(t_tmp_pool->take(nbytes, &p));
+        pool = t_tmp_pool;
+        return Status::Ok();
+    }
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
+    }
+    return Status::Ok();
+}
+
+void DevTmp::release() {
+    if (!p) return;
+    if (pool)
+        pool->give_back(p);
+    else
+        (void)hipFree(p);
+    p = nullptr;
+    pool = nullptr;
+}
+
+TmpScope::TmpScope(hipStream_t s) {
+    if (t_tmp_pool) return;
+    own = new TmpPool();
+    own->stream = s;
+    t_tmp_pool = own;
+}
+
+TmpScope::~TmpScope() {
+    if (!own) return;
+    t_tmp_pool = nullptr;
+    // no queued kernel may still read a block when it is freed
+    (void)hipStreamSynchronize(own->stream);
+    for (const TmpPool::Block &k : own->blocks) (void)hipFree(k.base);
+    delete own;
+}
+
 namespace {
 
 constexpr int kBlock = 256;
 
-// Temporary device buffer freed at scope exit.
-struct Tmp {
-    void *p = nullptr;
-    ~Tmp() {
-        if (p) (void)hipFree(p);
-    }
-    Status alloc(size_t n) {
-        hipError_t e = hipMalloc(&p, n ? n : 16);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
-        }
-        return Status::Ok();
-    }
-    template <class T> T *as() { return (T *)p; }
-};
+using Tmp = DevTmp;
 
 // ------------------------------------------------------------------------------------------
 // A1: positions. One thread per group; every operation rounded to FP64 in the stated order
@@ -383,9 +469,9 @@ Status scan_exclusive(uint32_t *data, int64_t n, uint32_t *ws, hipStream_t s) {
 
 Status scan_exclusive(uint32_t *data, int64_t n, hipStream_t s) {
     Tmp ws;
-    MWG_TRY(ws.alloc(4 * (size_t)scan_ws_words(n)));
+    MWG_TRY(ws.alloc(4 * (size_t)scan_ws_words(n), s));
     MWG_TRY(scan_exclusive(data, n, ws.as<uint32_t>(), s));
-    MWG_HIP(hipStreamSynchronize(s));  // ws must outlive the kernels
+    if (!ws.pooled()) MWG_HIP(hipStreamSynchronize(s));  // ws must outlive the kernels
     return Status::Ok();
 }
 
@@ -398,7 +484,7 @@ Status radix_sort(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *
     const int nblocks = (int)((n + kSortChunk - 1) / kSortChunk);
     const int64_t nh = (int64_t)256 * std::max(nblocks, 1);
     Tmp ws;
-    MWG_TRY(ws.alloc(4 * (size_t)(nh + scan_ws_words(nh))));
+    MWG_TRY(ws.alloc(4 * (size_t)(nh + scan_ws_words(nh)), s));
     uint32_t *hist = ws.as<uint32_t>(), *sws = hist + nh;
     uint32_t *kin = keys, *kout = keys_alt, *vout = vals;
     const uint32_t *vin = vals_init;
@@ -418,7 +504,7 @@ Status radix_sort(uint32_t *keys, uint32_t *keys_alt, uint32_t *vals, uint32_t *
     }
     *keys_out = kin;
     *vals_out = const_cast<uint32_t *>(vin); // after a pass vin is vals or vals_alt
-    MWG_HIP(hipStreamSynchronize(s));  // the scratch must outlive the kernels
+    if (!ws.pooled()) MWG_HIP(hipStreamSynchronize(s));  // the scratch must outlive the kernels
     return Status::Ok();
 }
 
@@ -498,7 +584,7 @@ Status stage_input(const T *src, size_t count, int mem, Tmp &tmp, const T **dst,
         *dst = src;
         return Status::Ok();
     }
-    MWG_TRY(tmp.alloc(sizeof(T) * count));
+    MWG_TRY(tmp.alloc(sizeof(T) * count, s));
     MWG_HIP(hipMemcpyAsync(tmp.p, src, sizeof(T) * count, hipMemcpyHostToDevice, s));
     *dst = (const T *)tmp.p;
     return Status::Ok();
@@ -549,10 +635,10 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     const bool resort = !(L.tile == I.sorted_tile && L.order == I.sorted_order);
     if (resort) {
         Tmp keys, keys2, vals, vals2;
-        MWG_TRY(keys.alloc(4 * ng));
-        MWG_TRY(keys2.alloc(4 * ng));
-        MWG_TRY(vals.alloc(4 * ng));
-        MWG_TRY(vals2.alloc(4 * ng));
+        MWG_TRY(keys.alloc(4 * ng, s));
+        MWG_TRY(keys2.alloc(4 * ng, s));
+        MWG_TRY(vals.alloc(4 * ng, s));
+        MWG_TRY(vals2.alloc(4 * ng, s));
         uint32_t *skeys = nullptr, *sperm = nullptr;
         if (ng > 0) {
             hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, I.nx, I.ny, L.order,
@@ -564,8 +650,8 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         }
         // tile bounds
         Tmp tstart, tend;
-        MWG_TRY(tstart.alloc(4 * ntiles));
-        MWG_TRY(tend.alloc(4 * ntiles));
+        MWG_TRY(tstart.alloc(4 * ntiles, s));
+        MWG_TRY(tend.alloc(4 * ntiles, s));
         MWG_TRY(launch_fill_u32(tstart.as<uint32_t>(), ntiles, 0, s));
         MWG_TRY(launch_fill_u32(tend.as<uint32_t>(), ntiles, 0, s));
         if (nk > 0) {
@@ -882,7 +968,7 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     // Index arrays must stay inside the arrays they index (checked once, on the device).
     {
         Tmp bad;
-        MWG_TRY(bad.alloc(sizeof(unsigned long long)));
+        MWG_TRY(bad.alloc(sizeof(unsigned long long), s));
         MWG_TRY(launch_fill_u32(bad.as<uint32_t>(), 2, 0, s));
         if (a1 && d.nrow > 0) {
             hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a1,
@@ -939,7 +1025,7 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     I.pos = (uint32_t *)p;
     const int64_t pos_blocks = std::max<int64_t>(1, (int64_t)grid1d(ng));
     Tmp counts;
-    MWG_TRY(counts.alloc(3 * sizeof(unsigned long long) + 12 * (size_t)pos_blocks));
+    MWG_TRY(counts.alloc(3 * sizeof(unsigned long long) + 12 * (size_t)pos_blocks, s));
     MWG_TRY(launch_fill_u32(counts.as<uint32_t>(), 6 + 3 * pos_blocks, 0, s));
     PosArgs a;
     a.ngroups = ng;

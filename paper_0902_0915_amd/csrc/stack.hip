@@ -38,21 +38,6 @@ int bitlen(uint64_t v) {
     return r;
 }
 
-struct DevTmp {
-    void *p = nullptr;
-    ~DevTmp() {
-        if (p) (void)hipFree(p);
-    }
-    Status alloc(size_t n) {
-        if (hipMalloc(&p, n ? n : 16) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed", n);
-        }
-        return Status::Ok();
-    }
-    template <class T> T *as() { return (T *)p; }
-};
 
 // Footprint tile span of a kept group: tiles [x0, x1] x [y0, y1].
 __device__ inline void span(uint32_t p, int h, int T, int &x0, int &x1, int &y0, int &y1) {
@@ -116,11 +101,18 @@ struct StackArgs {
     const WorkItem *work;
     float2 *grid;
     int nx, ny, T, ntx, O, nchan, accumulate;
+    // per clipped footprint width n (1 ... 64): the rows one round of 64 lanes covers
+    // (64 / n) and the multiplier m = ceil(2^16 / n) with lane / n = (lane * m) >> 16 for
+    // every lane < 64, so that a candidate needs no integer division
+    int rounds_rows[65], div_mul[65];
 };
 
 __device__ inline float rl_f(float x, int j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
+
+// Row rounds of a candidate's clipped footprint whose tap loads are issued together.
+constexpr int kStackRounds = 8;
 
 // One wavefront per work item (tile, candidate range, row band); private LDS tile.
 template <int NPOL>
@@ -144,15 +136,19 @@ __global__ __launch_bounds__(512) void k_grid_stack(StackArgs a, int nwork) {
 
     for (int base = wk.begin; base < wk.end; base += 64) {
         const int cnt = min(64, wk.end - base);
-        // lane j stages candidate j: position, kernel, multiplied visibilities
+        // lane j stages candidate j: position, kernel support and offset, multiplied
+        // visibilities (all loads of the batch in flight together)
         uint32_t qp = kDropped;
-        int qk = 0;
+        int qS = 1;
+        int64_t qoff = 0;
         float2 qv[NPOL];
         for (int p = 0; p < NPOL; p++) qv[p] = make_float2(0.f, 0.f);
         if (lane < cnt) {
             const uint32_t g = a.pairs[base + lane];
             qp = a.pos[g];
-            qk = a.kidx[g];
+            const int qk = a.kidx[g];
+            qS = a.ksup[qk];
+            qoff = a.koff[qk];
             float mr = a.w ? a.w[g] : 1.0f, mi = 0.0f;
             if (a.gains) {
                 const uint32_t an = a.ants[(int64_t)g / a.nchan];
@@ -168,8 +164,10 @@ __global__ __launch_bounds__(512) void k_grid_stack(StackArgs a, int nwork) {
         }
         for (int j = 0; j < cnt; j++) {
             const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)qp, j);
-            const int k = __builtin_amdgcn_readlane(qk, j);
-            const int S = a.ksup[k];
+            const int S = __builtin_amdgcn_readlane(qS, j);
+            const uint32_t olo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)qoff, j);
+            const uint32_t ohi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)qoff >> 32), j);
+            const int64_t koff = (int64_t)(((uint64_t)ohi << 32) | olo);
             const int h = (S - 1) / 2;
             const int cx = (int)(p & 0xFFFu), cy = (int)((p >> 12) & 0xFFFu);
             const int px = (int)((p >> 24) & 0xFu), py = (int)(p >> 28);
@@ -180,21 +178,33 @@ __global__ __launch_bounds__(512) void k_grid_stack(StackArgs a, int nwork) {
 #pragma unroll
             for (int q = 0; q < NPOL; q++) v[q] = make_float2(rl_f(qv[q].x, j), rl_f(qv[q].y, j));
             const int ncol = xb - xa + 1;
-            const int rpi = 64 / ncol;
-            const int rl = lane / ncol, cl = lane - rl * ncol;
-            const float2 *kb = a.kstack + a.koff[k] + ((int64_t)(py * a.O + px) * S) * S;
-            for (int y0 = ya; y0 <= yb; y0 += rpi) {
-                const int yy = y0 + rl;
-                if (rl < rpi && yy <= yb) {
-                    const int xx = xa + cl;
-                    const float2 K = kb[(yy - cy + h) * S + (xx - cx + h)];
-                    const int o = (yy - ty0) * T + (xx - tx0);
+            const int rpi = a.rounds_rows[ncol];
+            const int rl = (lane * a.div_mul[ncol]) >> 16, cl = lane - rl * ncol;
+            const bool on = rl < rpi;
+            const float2 *kb = a.kstack + koff + ((int64_t)(py * a.O + px) * S) * S + (cl + xa - cx + h);
+            const int o0 = (xa + cl - tx0);
+            // the clipped footprint in chunks of kStackRounds row rounds: every tap load of a
+            // chunk is issued before any of its LDS read-modify-writes, so a candidate waits
+            // for the cache about once per chunk instead of once per row round
+            for (int y0 = ya; y0 <= yb; y0 += kStackRounds * rpi) {
+                float2 K[kStackRounds];
 #pragma unroll
-                    for (int q = 0; q < NPOL; q++) {
-                        float2 acc = tile[q * T * T + o];
-                        acc.x += K.x * v[q].x - K.y * v[q].y;
-                        acc.y += K.x * v[q].y + K.y * v[q].x;
-                        tile[q * T * T + o] = acc;
+                for (int it = 0; it < kStackRounds; it++) {
+                    const int yy = y0 + it * rpi + rl;
+                    K[it] = (on && yy <= yb) ? kb[(int64_t)(yy - cy + h) * S] : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int it = 0; it < kStackRounds; it++) {
+                    const int yy = y0 + it * rpi + rl;
+                    if (on && yy <= yb) {
+                        const int o = (yy - ty0) * T + o0;
+#pragma unroll
+                        for (int q = 0; q < NPOL; q++) {
+                            float2 acc = tile[q * T * T + o];
+                            acc.x += K[it].x * v[q].x - K[it].y * v[q].y;
+                            acc.y += K[it].x * v[q].y + K[it].y * v[q].x;
+                            tile[q * T * T + o] = acc;
+                        }
                     }
                 }
             }
@@ -349,7 +359,7 @@ Status build_stack_schedule(Instance &I, const Launch &L, hipStream_t s) {
     I.ntx = ntx;
     I.nty = nty;
     DevTmp counts;
-    MWG_TRY(counts.alloc(4 * (size_t)(ng + 1)));
+    MWG_TRY(counts.alloc(4 * (size_t)(ng + 1), s));
     MWG_TRY(launch_fill_u32(counts.as<uint32_t>(), ng + 1, 0, s));
     if (ng > 0) {
         hipLaunchKernelGGL(k_pair_count, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, I.kidx_orig, I.ksup,
@@ -368,11 +378,11 @@ Status build_stack_schedule(Instance &I, const Launch &L, hipStream_t s) {
     int nonempty = 0;
     if (npairs > 0) {
         DevTmp keys, keys2, vals, vals2, vinit;
-        MWG_TRY(keys.alloc(4 * (size_t)npairs));
-        MWG_TRY(keys2.alloc(4 * (size_t)npairs));
-        MWG_TRY(vals.alloc(4 * (size_t)npairs));
-        MWG_TRY(vals2.alloc(4 * (size_t)npairs));
-        MWG_TRY(vinit.alloc(4 * (size_t)npairs));
+        MWG_TRY(keys.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(keys2.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(vals.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(vals2.alloc(4 * (size_t)npairs, s));
+        MWG_TRY(vinit.alloc(4 * (size_t)npairs, s));
         hipLaunchKernelGGL(k_pair_emit, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, I.kidx_orig, I.ksup, ng,
                            T, ntx, counts.as<uint32_t>(), sbits, keys.as<uint32_t>(), vinit.as<uint32_t>());
         MWG_HIP(hipGetLastError());
@@ -384,8 +394,8 @@ Status build_stack_schedule(Instance &I, const Launch &L, hipStream_t s) {
         I.npairs = npairs;
         MWG_HIP(hipMemcpyAsync(I.pairs, sv, 4 * (size_t)npairs, hipMemcpyDeviceToDevice, s));
         DevTmp tstart, tend;
-        MWG_TRY(tstart.alloc(4 * ntiles));
-        MWG_TRY(tend.alloc(4 * ntiles));
+        MWG_TRY(tstart.alloc(4 * ntiles, s));
+        MWG_TRY(tend.alloc(4 * ntiles, s));
         MWG_TRY(launch_fill_u32(tstart.as<uint32_t>(), ntiles, 0, s));
         MWG_TRY(launch_fill_u32(tend.as<uint32_t>(), ntiles, 0, s));
         hipLaunchKernelGGL(k_pair_bounds, dim3(grid1d(npairs)), dim3(kBlock), 0, s, sk, (int64_t)npairs, sbits,
@@ -449,6 +459,10 @@ Status launch_grid_stack(Instance &I, const float2 *vis, const float2 *gains, fl
     a.O = I.O;
     a.nchan = I.nchan;
     a.accumulate = 1; // the grid was zeroed above in overwrite mode
+    for (int n = 1; n <= 64; n++) {
+        a.rounds_rows[n] = 64 / n;
+        a.div_mul[n] = (65536 + n - 1) / n;
+    }
     switch (I.npol) {
     case 1: return grid_stack_npol<1>(I, a, s);
     case 2: return grid_stack_npol<2>(I, a, s);

@@ -23,21 +23,7 @@ constexpr int kBlock = 256;
 
 unsigned grid1d(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-struct Tmp {
-    void *p = nullptr;
-    ~Tmp() {
-        if (p) (void)hipFree(p);
-    }
-    Status alloc(size_t n) {
-        if (hipMalloc(&p, n ? n : 16) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return make_error(MW_ERR_ALLOC, "hipMalloc(%zu) failed", n);
-        }
-        return Status::Ok();
-    }
-    template <class T> T *as() { return (T *)p; }
-};
+using Tmp = DevTmp;
 
 __device__ inline int64_t cell_of(uint32_t p, int nx) {
     return (int64_t)((p >> 12) & 0xFFFu) * nx + (int64_t)(p & 0xFFFu);
@@ -138,7 +124,7 @@ Status apply_density_weighting(Instance &I, int mode, float robust, const float 
     const int64_t ng = I.ngroups;
     if (ng == 0) return Status::Ok();
     Tmp mx;
-    MWG_TRY(mx.alloc(4));
+    MWG_TRY(mx.alloc(4, s));
     MWG_HIP(hipMemsetAsync(mx.p, 0, 4, s));
     hipLaunchKernelGGL(k_wmax, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, w_in, ng, mx.as<uint32_t>());
     MWG_HIP(hipGetLastError());
@@ -162,15 +148,15 @@ Status apply_density_weighting(Instance &I, int mode, float robust, const float 
     const double scale = std::ldexp(1.0, e), inv = std::ldexp(1.0, -e);
     const int64_t ncell = (int64_t)I.nx * I.ny;
     Tmp cells;
-    MWG_TRY(cells.alloc(8 * (size_t)ncell));
+    MWG_TRY(cells.alloc(8 * (size_t)ncell, s));
     MWG_HIP(hipMemsetAsync(cells.p, 0, 8 * (size_t)ncell, s));
     hipLaunchKernelGGL(k_density, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, w_in, ng, I.nx, scale,
                        cells.as<unsigned long long>());
     MWG_HIP(hipGetLastError());
     Tmp part, tot;
     const int64_t nb = grid1d(ncell);
-    MWG_TRY(part.alloc(sizeof(double2) * (size_t)nb));
-    MWG_TRY(tot.alloc(sizeof(double2)));
+    MWG_TRY(part.alloc(sizeof(double2) * (size_t)nb, s));
+    MWG_TRY(tot.alloc(sizeof(double2), s));
     if (mode == 2) {
         hipLaunchKernelGGL(k_density_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, cells.as<unsigned long long>(),
                            ncell, inv, part.as<double2>());
