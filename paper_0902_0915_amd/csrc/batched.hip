@@ -410,29 +410,30 @@ Status refresh_desc(Batch &B, const void *const *vis, const void *const *gains, 
 // (variant 4, merge flush, same tile and waves); other plans run instance by instance.
 Status batch_prepare(Plan &P, hipStream_t s) {
     P.batch = nullptr;
-    if (P.inst.size() < 2) return Status::Ok();
-    // Sparse batches (fewer than 64 kept groups per non-empty 8 x 8 tile on average) take
+    // Sparse batches (fewer than 64 kept groups per occupied 8 x 8 tile on average) take
     // 16 x 16 tiles: a quarter of the work items, each staging and flushing less halo per
     // group. The batch as a whole still has items enough to fill the chip, which one sparse
-    // instance on its own does not, so single-instance plans keep 8 x 8.
+    // instance on its own does not, so single-instance plans keep 8 x 8. The choice needs only
+    // the occupied-tile counts of the positions pass, so an instance whose schedule was
+    // deferred is sorted once, at its final tile.
     {
-        bool retile = true;
+        bool retile = P.inst.size() >= 2;
         int64_t kept = 0, tiles = 0;
         for (const Instance *I : P.inst) {
             retile = retile && !I->stacks && !I->tile_fixed && I->L.variant == 4 && I->L.flush == 2 &&
                      I->L.tile == 8 && I->L.schedule == 1 &&
                      wavetiles_lds(I->npol, 16, I->W, I->O, I->L.wg_waves) <= 160 * 1024;
             kept += I->nkept;
-            tiles += I->ntiles_nonempty;
+            tiles += I->ntiles8;
         }
-        if (retile && tiles > 0 && kept < 64 * tiles) {
-            for (Instance *I : P.inst) {
-                Launch L = I->L;
-                L.tile = 16;
-                MWG_TRY(rebuild_schedule(*I, L, s));
-            }
+        retile = retile && tiles > 0 && kept < 64 * tiles;
+        for (Instance *I : P.inst) {
+            Launch L = I->L;
+            if (retile) L.tile = 16;
+            if (!I->scheduled || L.tile != I->L.tile) MWG_TRY(schedule_instance(*I, L, s));
         }
     }
+    if (P.inst.size() < 2) return Status::Ok();
     const Instance &I0 = *P.inst[0];
     for (const Instance *I : P.inst) {
         if (I->stacks || I->npol != I0.npol || I->W != I0.W || I->O != I0.O || I->L.variant != 4 ||
@@ -516,10 +517,7 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         }
         max_nant = std::max(max_nant, I.nant);
         {
-            const int nw = owner ? I.nowork : I.nwork;
-            std::vector<WorkItem> wl((size_t)nw);
-            if (nw > 0)
-                MWG_HIP(hipMemcpy(wl.data(), owner ? I.owork : I.work, sizeof(WorkItem) * nw, hipMemcpyDeviceToHost));
+            const std::vector<WorkItem> &wl = owner ? I.h_owork : I.h_work;
             d.item0 = (int32_t)items.size();
             for (const WorkItem &wk : wl)
                 items.push_back({i, wk.tile, wk.begin, wk.end, owner ? I.pperm : I.perm, owner ? I.pcode : I.scode});
@@ -562,24 +560,19 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         // (instance, block) pairs of flush-2 instances: all merge blocks, then all zero
         // blocks; (instance, tile) pairs of the zero tiles of flush-3 instances
         std::vector<int2> mp, zt;
-        std::vector<std::vector<int32_t>> lists(B->ninst);
         for (int i = 0; i < B->ninst; i++) {
             const Instance &I = *P.inst[i];
             if (I.L.flush == 3) {
-                std::vector<int32_t> z((size_t)I.n_ozero);
-                if (!z.empty()) MWG_HIP(hipMemcpy(z.data(), I.ozero, 4 * z.size(), hipMemcpyDeviceToHost));
-                for (int32_t t : z) zt.push_back(make_int2(i, t));
+                for (int32_t t : I.h_ozero) zt.push_back(make_int2(i, t));
                 continue;
             }
-            lists[i].resize((size_t)(I.n_mblocks + I.n_zblocks));
-            if (!lists[i].empty())
-                MWG_HIP(hipMemcpy(lists[i].data(), I.mblocks, 4 * lists[i].size(), hipMemcpyDeviceToHost));
-            for (int k = 0; k < I.n_mblocks; k++) mp.push_back(make_int2(i, lists[i][k]));
+            for (int k = 0; k < I.n_mblocks; k++) mp.push_back(make_int2(i, I.h_mblocks[k]));
         }
         B->merge_blocks = (int64_t)mp.size();
         for (int i = 0; i < B->ninst; i++)
             if (P.inst[i]->L.flush != 3)
-                for (int k = P.inst[i]->n_mblocks; k < (int)lists[i].size(); k++) mp.push_back(make_int2(i, lists[i][k]));
+                for (int k = P.inst[i]->n_mblocks; k < (int)P.inst[i]->h_mblocks.size(); k++)
+                    mp.push_back(make_int2(i, P.inst[i]->h_mblocks[k]));
         B->zero_blocks = (int64_t)mp.size() - B->merge_blocks;
         B->ztiles = (int64_t)zt.size();
         MWG_TRY(B->arena.alloc(&p, sizeof(int2) * std::max<size_t>(mp.size(), 1)));

@@ -128,6 +128,8 @@ struct Instance {
     bool tile_fixed = false;  // the caller chose the tile (or asked the autotuner)
     bool flush_fixed = false; // the caller chose the flush
     int ntx = 0, nty = 0, ntiles_nonempty = 0, nwork = 0;
+    int64_t ntiles8 = 0;     // occupied 8 x 8 tiles (counted for plans of several instances)
+    bool scheduled = false;  // sort and work list built for the launch L
     int max_work_groups = 0;  // largest work item
     int sorted_tile = 0, sorted_order = 0;   // the (tile, order) perm is currently sorted by
     std::vector<int32_t> h_tstart, h_tend;  // tile bounds of that sort (host)
@@ -174,6 +176,9 @@ struct Instance {
     uint32_t *psant = nullptr;    // [npairs] antenna pairs (or null)
     int32_t *ozero = nullptr;     // [n_ozero] output tiles without candidates
     size_t cap_pairs = 0, cap_owork = 0, cap_ozero = 0;
+    // host copies of the lists built on the host (the batched plan reads them back from here)
+    std::vector<WorkItem> h_work, h_owork;
+    std::vector<int32_t> h_mblocks, h_ozero;
     float *partial = nullptr;     // merge flush scratch: [nwork][R*R][2*npol] (cell-major)
     size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)
@@ -191,10 +196,14 @@ struct Instance {
     // prediction and calibration (calib.hip)
     double *uvw_d = nullptr;      // [nrow][3] metres
     double *kf_d = nullptr;       // [nchan] f / c, turns per metre
-    int32_t *cal_start = nullptr; // [nant + 1] CSR of each antenna's rows
-    int32_t *cal_entry = nullptr; // [2 nrow] row << 1 | (0: the row's ant1, 1: its ant2)
-    int32_t *cal_partner = nullptr; // [2 nrow] the row's other antenna
-    float4 *cal_pq = nullptr;     // [nrow] per-row sums (Re P, Im P, Q, 0)
+    int64_t cal_npair = 0;        // antenna pairs (baselines) among the rows
+    uint32_t *cal_pant = nullptr; // [npair] a1 | a2 << 16
+    int32_t *cal_pstart = nullptr; // [npair + 1] CSR of each pair's rows
+    int32_t *cal_prows = nullptr; // [nrow]
+    int32_t *cal_start = nullptr; // [nant + 1] CSR of each antenna's pairs
+    int32_t *cal_entry = nullptr; // [2 npair] pair << 1 | (0: the pair's ant1, 1: its ant2)
+    int32_t *cal_partner = nullptr; // [2 npair] the pair's other antenna
+    float4 *cal_pq = nullptr;     // [npair] per-pair sums (Re P, Im P, Q, 0)
     float2 *cal_g = nullptr;      // [nant] second gain buffer of the iteration
     double *cal_red = nullptr;    // [2 nant] per-antenna |step|^2 and |g|^2 of the last iteration
     void *src_d = nullptr, *src_h = nullptr;  // source table, device and pinned host staging
@@ -220,7 +229,11 @@ void prolate_tables(int W, int O, int nx, int ny, std::vector<float> &table,
                     std::vector<float> &corr_x, std::vector<float> &corr_y);
 
 // plan.hip
-Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *t, hipStream_t s);
+// schedule: build the sort and work list now (false: the caller does, with schedule_instance,
+// once the launch is settled); count_tiles: count the occupied 8 x 8 tiles (ntiles8)
+Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *t, hipStream_t s, bool schedule = true,
+                      bool count_tiles = false);
+Status schedule_instance(Instance &I, const Launch &L, hipStream_t s);
 Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s);
 
 // stack.hip

@@ -222,6 +222,8 @@ Status build_owner_schedule(Instance &I, int64_t cap, bool *built, hipStream_t s
     I.owner_tile = T;
     I.nowork = (int)items.size();
     I.n_ozero = (int)zero.size();
+    I.h_owork = items;
+    I.h_ozero = zero;
     I.max_owner_groups = maxn;
     I.npairs_owner = npairs;
     *built = true;

@@ -277,6 +277,36 @@ __global__ void k_sum_counts(const uint32_t *cnt, int64_t nblocks, unsigned long
     }
 }
 
+// Occupied 8 x 8 tiles: one bit per tile, set by the first group found in it (a group that
+// sees its bit already set issues no atomic), then a population count. A batched plan picks its
+// tile size from this count before any schedule is built.
+constexpr int kCountTile = 8;
+
+__global__ void k_mark_tiles(const uint32_t *pos, int64_t n, int ntx, uint32_t *bits) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const uint32_t p = pos[g];
+    if (p == kDropped) return;
+    const int t = (int)(((p >> 12) & 0xFFFu) / kCountTile) * ntx + (int)((p & 0xFFFu) / kCountTile);
+    uint32_t *w = bits + (t >> 5);
+    const uint32_t m = 1u << (t & 31);
+    if (!(__atomic_load_n(w, __ATOMIC_RELAXED) & m)) atomicOr(w, m);
+}
+
+__global__ void k_popcount(const uint32_t *bits, int64_t nwords, unsigned long long *out) {
+    __shared__ unsigned long long part[kBlock / 64];
+    unsigned long long v = 0;
+    for (int64_t i = threadIdx.x; i < nwords; i += blockDim.x) v += (unsigned long long)__popc(bits[i]);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int k = 0; k < kBlock / 64; k++) s += part[k];
+        *out = s;
+    }
+}
+
 // Sort keys: tile-major, then cell within the tile (order 1) or nothing (order 2: the stable
 // sort keeps input order). Dropped groups get the all-ones key of the sorted width.
 // Rank of cell (cx, cy) among the cells of its tile ordered by their line across the radius
@@ -672,18 +702,16 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     std::vector<WorkItem> items;
     int nonempty = 0;
     for (int64_t t = 0; t < ntiles; t++) {
-        const int64_t cnt = he[t] - hs[t];
+        const int32_t b = hs[t], cnt = he[t] - hs[t];
         if (cnt <= 0) continue;
         nonempty++;
-        const int64_t pieces = (cnt + L.split - 1) / L.split;
-        for (int64_t q = 0; q < pieces; q++) {
-            WorkItem w;
-            w.tile = (int32_t)t;
-            w.begin = (int32_t)(hs[t] + cnt * q / pieces);
-            w.end = (int32_t)(hs[t] + cnt * (q + 1) / pieces);
-            w.pad = 0;
-            items.push_back(w);
+        if (cnt <= L.split) {
+            items.push_back({(int32_t)t, b, b + cnt, 0});
+            continue;
         }
+        const int64_t pieces = (cnt + L.split - 1) / L.split;
+        for (int64_t q = 0; q < pieces; q++)
+            items.push_back({(int32_t)t, (int32_t)(b + cnt * q / pieces), (int32_t)(b + cnt * (q + 1) / pieces), 0});
     }
     if (L.schedule == 2) {
         // Z-order of tile coordinates (the split pieces of a tile stay together), so that
@@ -697,9 +725,15 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
             return morton(a.tile) < morton(b.tile);
         });
     } else {
-        std::stable_sort(items.begin(), items.end(), [](const WorkItem &a, const WorkItem &b) {
-            return (a.end - a.begin) > (b.end - b.begin);
-        });
+        // largest first, ties in tile order: a stable counting sort on the item size
+        int maxsz = 0;
+        for (const WorkItem &w : items) maxsz = std::max(maxsz, w.end - w.begin);
+        std::vector<int32_t> at((size_t)maxsz + 2, 0);
+        for (const WorkItem &w : items) at[maxsz - (w.end - w.begin) + 1]++;
+        for (int k = 0; k <= maxsz; k++) at[k + 1] += at[k];
+        std::vector<WorkItem> sorted(items.size());
+        for (const WorkItem &w : items) sorted[at[maxsz - (w.end - w.begin)]++] = w;
+        items.swap(sorted);
     }
     // Schedule 2: the launch's workgroups are dealt to the 8 XCDs round-robin by index; the
     // logical workgroups (wg_waves consecutive work items each) are cut into 8 contiguous
@@ -754,25 +788,25 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     std::vector<int32_t> mlist;
     int nmerge = 0;
     {
+        // a block is reached when it meets the haloed extent [tx T - h, tx T + T - 1 + h] of
+        // a tile with work items (per axis; blocks listed in row-major order)
         const int bpr = (I.nx + kMergeB - 1) / kMergeB, bpc = (I.ny + kMergeB - 1) / kMergeB;
-        const int h = (I.W - 1) / 2;
-        std::vector<int32_t> zero;
+        const int h = (I.W - 1) / 2, T = L.tile;
+        std::vector<uint8_t> reach((size_t)bpr * bpc, 0);
+        for (int64_t t = 0; t < ntiles; t++) {
+            if (tw[t + 1] == tw[t]) continue;
+            const int tx = (int)(t % ntx), ty = (int)(t / ntx);
+            const int bx0 = std::max(0, tx * T - h) / kMergeB, bx1 = std::min(bpr - 1, (tx * T + T - 1 + h) / kMergeB);
+            const int by0 = std::max(0, ty * T - h) / kMergeB, by1 = std::min(bpc - 1, (ty * T + T - 1 + h) / kMergeB);
+            for (int by = by0; by <= by1; by++)
+                for (int bx = bx0; bx <= bx1; bx++) reach[(size_t)by * bpr + bx] = 1;
+        }
         mlist.reserve((size_t)bpr * bpc);
-        for (int by = 0; by < bpc; by++)
-            for (int bx = 0; bx < bpr; bx++) {
-                const int x0 = bx * kMergeB, y0 = by * kMergeB;
-                const int tx_lo = std::max(0, x0 - h) >> tb, tx_hi = std::min(ntx - 1, (x0 + kMergeB - 1 + h) >> tb);
-                const int ty_lo = std::max(0, y0 - h) >> tb, ty_hi = std::min(nty - 1, (y0 + kMergeB - 1 + h) >> tb);
-                bool any = false;
-                for (int ty = ty_lo; ty <= ty_hi && !any; ty++)
-                    for (int tx = tx_lo; tx <= tx_hi && !any; tx++) {
-                        const int64_t t = (int64_t)ty * ntx + tx;
-                        any = tw[t + 1] > tw[t];
-                    }
-                (any ? mlist : zero).push_back(by * bpr + bx);
-            }
+        for (int b = 0; b < bpr * bpc; b++)
+            if (reach[b]) mlist.push_back(b);
         nmerge = (int)mlist.size();
-        mlist.insert(mlist.end(), zero.begin(), zero.end());
+        for (int b = 0; b < bpr * bpc; b++)
+            if (!reach[b]) mlist.push_back(b);
     }
     // (re)allocate schedule arrays: these are small; keep them in the arena
     I.L = L;
@@ -817,6 +851,8 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     MWG_HIP(hipMemcpyAsync(I.mblocks, mlist.data(), 4 * mlist.size(), hipMemcpyHostToDevice, s));
     I.n_mblocks = nmerge;
     I.n_zblocks = (int)mlist.size() - nmerge;
+    I.h_work = items;
+    I.h_mblocks = mlist;
     // Sorted per-group arrays follow the new permutation.
     if (nk > 0) {
         if (resort) {
@@ -836,6 +872,13 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         bool built = false;
         MWG_TRY(build_owner_schedule(I, 0, &built, s));
     }
+    return Status::Ok();
+}
+
+Status schedule_instance(Instance &I, const Launch &L, hipStream_t s) {
+    MWG_TRY(rebuild_schedule(I, L, s));
+    if (I.stacks) MWG_TRY(build_stack_schedule(I, L, s));
+    I.scheduled = true;
     return Status::Ok();
 }
 
@@ -934,7 +977,8 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
     return Status::Ok();
 }
 
-Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning, hipStream_t s) {
+Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning, hipStream_t s, bool schedule,
+                      bool count_tiles) {
     I.nx = d.nx;
     I.ny = d.ny;
     I.du = d.du;
@@ -1057,12 +1101,29 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
                            counts.as<unsigned long long>());
         MWG_HIP(hipGetLastError());
     }
-    unsigned long long hc[3] = {0, 0, 0};
+    unsigned long long hc[3] = {0, 0, 0}, h8 = 0;
+    Tmp tiles8;
+    if (count_tiles) {
+        const int ntx8 = (I.nx + kCountTile - 1) / kCountTile, nty8 = (I.ny + kCountTile - 1) / kCountTile;
+        const int64_t nwords = ((int64_t)ntx8 * nty8 + 31) / 32;
+        MWG_TRY(tiles8.alloc(8 + 4 * (size_t)nwords, s));
+        uint32_t *bits = tiles8.as<uint32_t>() + 2;
+        MWG_TRY(launch_fill_u32(bits, nwords, 0, s));
+        if (ng > 0) {
+            hipLaunchKernelGGL(k_mark_tiles, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, ntx8, bits);
+            MWG_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_popcount, dim3(1), dim3(kBlock), 0, s, bits, nwords,
+                           tiles8.as<unsigned long long>());
+        MWG_HIP(hipGetLastError());
+        MWG_HIP(hipMemcpyAsync(&h8, tiles8.p, sizeof h8, hipMemcpyDeviceToHost, s));
+    }
     MWG_HIP(hipMemcpyAsync(hc, counts.p, sizeof hc, hipMemcpyDeviceToHost, s));
     MWG_HIP(hipStreamSynchronize(s));
     I.nkept = (int64_t)hc[0];
     I.nflagged = (int64_t)hc[1];
     I.noutside = (int64_t)hc[2];
+    I.ntiles8 = (int64_t)h8;
 
     // Input-order copies the schedule gathers from (weights, packed antenna pairs, kernels).
     if (I.has_weights) {
@@ -1118,8 +1179,8 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     MWG_TRY(resolve_launch(I, tuning, &L));
     I.tile_fixed = tuning && tuning->tile != 0;
     I.flush_fixed = tuning && tuning->flush != 0;
-    MWG_TRY(rebuild_schedule(I, L, s));
-    if (I.stacks) MWG_TRY(build_stack_schedule(I, L, s));
+    I.L = L;
+    if (schedule) MWG_TRY(schedule_instance(I, L, s));
 
     // prediction and calibration state (uvw, frequencies, per-antenna row lists)
     MWG_TRY(build_calibration(I, uvw, freq, a1, a2, s));

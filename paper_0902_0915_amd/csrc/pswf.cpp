@@ -17,6 +17,9 @@
 #include "internal.h"
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 namespace mwg {
@@ -24,7 +27,8 @@ namespace mwg {
 namespace {
 
 struct Prolate {
-    std::vector<double> coef; // coefficient of P_{2j} (standard Legendre)
+    std::vector<double> coef;    // coefficient of P_{2j} (standard Legendre)
+    std::vector<double> ra, rb;  // recurrence factors (2k+1)/(k+1) and k/(k+1)
 };
 
 double legendre_a(int k) { return k == 0 ? 0.0 : k / std::sqrt((2.0 * k - 1.0) * (2.0 * k + 1.0)); }
@@ -94,6 +98,12 @@ Prolate solve(double c) {
     }
     if (at0 < 0)
         for (double &v : p.coef) v = -v;
+    p.ra.resize(2 * m);
+    p.rb.resize(2 * m);
+    for (int k = 0; k < 2 * m; k++) {
+        p.ra[k] = (2.0 * k + 1.0) / (k + 1.0);
+        p.rb[k] = k / (k + 1.0);
+    }
     return p;
 }
 
@@ -102,7 +112,7 @@ double evaluate(const Prolate &p, double eta) {
     double pm1 = 1.0, pk = eta, sum = p.coef[0];
     const int kmax = 2 * (int)p.coef.size() - 2;
     for (int k = 1; k < kmax; k++) {
-        double pk1 = ((2.0 * k + 1.0) * eta * pk - k * pm1) / (k + 1.0);
+        double pk1 = (p.ra[k] * eta * pk - p.rb[k] * pm1);
         pm1 = pk;
         pk = pk1;
         if ((k + 1) % 2 == 0) sum += p.coef[(k + 1) / 2] * pk;
@@ -112,8 +122,33 @@ double evaluate(const Prolate &p, double eta) {
 
 } // namespace
 
+// Tables depend only on (W, O, nx, ny) and plans of many instances repeat a few of them, so
+// they are computed once per process and kept (a few KiB each).
+struct TableKey {
+    int W, O, nx, ny;
+    bool operator<(const TableKey &o) const {
+        return std::tie(W, O, nx, ny) < std::tie(o.W, o.O, o.nx, o.ny);
+    }
+};
+struct TableEntry {
+    std::vector<float> table, corr_x, corr_y;
+};
+
 void prolate_tables(int W, int O, int nx, int ny, std::vector<float> &table,
                     std::vector<float> &corr_x, std::vector<float> &corr_y) {
+    static std::mutex mu;
+    static std::map<TableKey, TableEntry> cache;
+    const TableKey key{W, O, nx, ny};
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            table = it->second.table;
+            corr_x = it->second.corr_x;
+            corr_y = it->second.corr_y;
+            return;
+        }
+    }
     const double c = M_PI * W / 2.0;
     Prolate p = solve(c);
     const int h = (W - 1) / 2;
@@ -130,15 +165,23 @@ void prolate_tables(int W, int O, int nx, int ny, std::vector<float> &table,
         for (int t = 0; t < W; t++) table[(size_t)row * W + t] = (float)(vals[t] / sum);
     }
     const double at0 = evaluate(p, 0.0);
+    // psi_0 is even: pixel n/2 + d and n/2 - d take the same value, so each is evaluated once
     auto fill = [&](int n, std::vector<float> &out) {
         out.resize(n);
         for (int i = 0; i < n; i++) {
+            const int mirror = n - i;  // (mirror - n/2) = -(i - n/2) when n is even
+            if (n % 2 == 0 && i > n / 2 && mirror >= 0 && mirror < i) {
+                out[i] = out[mirror];
+                continue;
+            }
             double x = (i - n / 2.0) / n;
             out[i] = (float)(evaluate(p, 2.0 * x) / at0);
         }
     };
     fill(nx, corr_x);
     fill(ny, corr_y);
+    std::lock_guard<std::mutex> lk(mu);
+    cache.emplace(key, TableEntry{table, corr_x, corr_y});
 }
 
 } // namespace mwg
