@@ -274,9 +274,10 @@ mw_status mw_predict(mw_plan plan, int32_t inst, const double *sources, int32_t 
  * iterate, g_p = sum w z conj(R) / sum w |z|^2 over the samples involving p, and every second
  * iterate is averaged with the previous one. gains: device complex64 [nant], the starting
  * point in, the solution out (an antenna without weighted samples keeps its value). vis,
- * model: device complex64 [ngroups][npol]; weights: device float32 [ngroups] or NULL (= 1).
- * rel_step: device float32 [1] or NULL, receives ||g_i - g_(i-1)|| / ||g_i|| of the last
- * iteration. Needs an instance planned with antennas (else MW_ERR_STATE).
+ * model: device complex64 [ngroups][npol], 16-byte aligned (8 with one polarisation); weights:
+ * device float32 [ngroups] or NULL (= 1). rel_step: device float32 [1] or NULL, receives
+ * ||g_i - g_(i-1)|| / ||g_i|| of the last iteration. Needs an instance planned with antennas
+ * (else MW_ERR_STATE); misaligned arrays give MW_ERR_INVALID_ARG.
  */
 mw_status mw_solve_gains(mw_plan plan, int32_t inst, const void *vis, const void *model,
                          const float *weights, void *gains, int32_t niter, float *rel_step,
@@ -287,10 +288,10 @@ mw_status mw_solve_gains(mw_plan plan, int32_t inst, const void *vis, const void
  * call returns) are taken in decreasing |S|, ties in catalogue order. For each: the gains
  * toward it are solved (mw_solve_gains from unit gains, niter >= 1 iterations) from the current
  * residual against its prediction, and g[a1] conj(g[a2]) times the prediction is removed from
- * the residual. resid: device complex64 [ngroups][npol] (may equal vis; starts as vis);
- * gains: device complex64 [nsrc][nant], row k for catalogue entry k; rel_step: device float32
- * [nsrc] or NULL. The plan keeps a device and a pinned host copy of the catalogue (grown on
- * demand). Needs an instance planned with antennas.
+ * the residual. resid: device complex64 [ngroups][npol] (may equal vis; starts as vis), like
+ * vis 16-byte aligned (8 with one polarisation); gains: device complex64 [nsrc][nant], row k for
+ * catalogue entry k; rel_step: device float32 [nsrc] or NULL. The plan keeps a device and a
+ * pinned host copy of the catalogue (grown on demand). Needs an instance planned with antennas.
  */
 mw_status mw_peel(mw_plan plan, int32_t inst, const void *vis, const double *sources, int32_t nsrc,
                   const float *weights, int32_t niter, void *resid, void *gains, float *rel_step,

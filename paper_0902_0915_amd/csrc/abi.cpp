@@ -148,6 +148,18 @@ Status static_scratch(void **ptr, size_t *bytes) {
 } // namespace mwg
 
 
+namespace {
+
+mwg::Status check_inst(mw_plan plan, int32_t inst, mwg::Instance **out) {
+    mwg::Status s = check_plan(plan);
+    if (!s.ok()) return s;
+    mwg::Plan *P = (mwg::Plan *)plan;
+    if (inst < 0 || inst >= (int)P->inst.size()) return mwg::make_error(MW_ERR_INVALID_ARG, "inst out of range");
+    *out = P->inst[inst];
+    return mwg::Status::Ok();
+}
+} // namespace
+
 extern "C" {
 
 int32_t mw_abi_version(void) { return MW_ABI_VERSION; }
@@ -175,10 +187,13 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
             delete P;
             return fail(MW_ERR_HIP, "hipGetDevice failed (no GPU?)");
         }
+        // a plan of several instances settles its tile size across them before sorting any
+        const bool autotune = tuning && tuning->autotune;
+        const bool defer = ninst > 1 && !autotune;
         for (int i = 0; i < ninst; i++) {
             mwg::Instance *I = new mwg::Instance();
             P->inst.push_back(I);
-            mwg::Status s = mwg::build_instance(*I, inst[i], tuning, st);
+            mwg::Status s = mwg::build_instance(*I, inst[i], tuning, st, !defer, ninst > 1);
             if (!s.ok()) {
                 destroy_plan(P);
                 return fail(s);
@@ -186,7 +201,7 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
         }
         {
             // the tuner forms (and times) the batch itself; otherwise form it here
-            mwg::Status s = (tuning && tuning->autotune) ? mwg::autotune_plan(*P, *tuning, st)
+            mwg::Status s = autotune ? mwg::autotune_plan(*P, *tuning, st)
                             : ninst > 1                  ? mwg::batch_prepare(*P, st)
                                                          : mwg::Status::Ok();
             if (!s.ok()) {
@@ -365,17 +380,6 @@ mw_status mw_stokes(mw_plan plan, const void *const *images, const void *const *
     }
 }
 
-namespace {
-mwg::Status check_inst(mw_plan plan, int32_t inst, mwg::Instance **out) {
-    mwg::Status s = check_plan(plan);
-    if (!s.ok()) return s;
-    mwg::Plan *P = (mwg::Plan *)plan;
-    if (inst < 0 || inst >= (int)P->inst.size()) return mwg::make_error(MW_ERR_INVALID_ARG, "inst out of range");
-    *out = P->inst[inst];
-    return mwg::Status::Ok();
-}
-} // namespace
-
 mw_status mw_predict(mw_plan plan, int32_t inst, const double *sources, int32_t nsrc, const void *gains, void *vis,
                      int32_t accumulate, void *stream) {
     try {
@@ -401,6 +405,10 @@ mw_status mw_solve_gains(mw_plan plan, int32_t inst, const void *vis, const void
         if (!I->has_ants) return fail(MW_ERR_STATE, "gain solving needs an instance planned with antennas");
         if (!gains || ((!vis || !model) && I->ngroups > 0))
             return fail(MW_ERR_INVALID_ARG, "vis, model and gains must be device pointers");
+        const uintptr_t align = I->npol >= 2 ? 16 : 8;
+        if (((uintptr_t)vis % align) || ((uintptr_t)model % align) || ((uintptr_t)gains % 8))
+            return fail(mwg::make_error(MW_ERR_INVALID_ARG, "vis and model must be %d-byte aligned, gains 8-byte",
+                                        (int)align));
         s = mwg::launch_solve_gains(*I, (const float2 *)vis, (const float2 *)model, weights, (float2 *)gains, niter,
                                     rel_step, (hipStream_t)stream);
         return s.ok() ? ok() : fail(s);
@@ -418,6 +426,10 @@ mw_status mw_peel(mw_plan plan, int32_t inst, const void *vis, const double *sou
         if (!I->has_ants) return fail(MW_ERR_STATE, "peeling needs an instance planned with antennas");
         if (((!vis || !resid) && I->ngroups > 0) || (nsrc > 0 && (!sources || !gains)))
             return fail(MW_ERR_INVALID_ARG, "vis, resid, gains (device) and sources (host) are required");
+        const uintptr_t align = I->npol >= 2 ? 16 : 8;
+        if (((uintptr_t)vis % align) || ((uintptr_t)resid % align) || ((uintptr_t)gains % 8))
+            return fail(mwg::make_error(MW_ERR_INVALID_ARG, "vis and resid must be %d-byte aligned, gains 8-byte",
+                                        (int)align));
         s = mwg::launch_peel(*I, (const float2 *)vis, sources, nsrc, weights, niter, (float2 *)resid, (float2 *)gains,
                              rel_step, (hipStream_t)stream);
         return s.ok() ? ok() : fail(s);

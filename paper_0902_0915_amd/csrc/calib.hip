@@ -12,24 +12,27 @@
 // iteration of Salvini & Wijnholds (2014, "StEFCal") solves, for every antenna p with the
 // others fixed, g_p = sum w z conj(R) / sum w |z|^2 over all samples involving p (see the
 // oracle for the derivation), damping every second iterate by averaging it with the previous
-// one. With scalar gains, every sample of one row (one baseline at one time) has the same
-// antenna pair, so the sums factor through two per-row numbers that do not depend on g:
-//     P_r = sum_{chan, pol} w conj(M) V,    Q_r = sum w |M|^2.
-// Antenna p then needs num_p = sum_{a1(r) = p} g[a2] P_r + sum_{a2(r) = p} g[a1] conj(P_r) and
-// den_p = sum_{a1 = p} |g[a2]|^2 Q_r + sum_{a2 = p} |g[a1]|^2 Q_r. One pass over the
-// visibilities forms (P, Q); every iteration after that reads only the rows' (P, Q) through a
-// per-antenna list of rows built with the plan, so the iterations cost almost nothing.
+// one. With scalar gains constant over the data, every sample of one antenna pair has the same
+// two gains, so the sums factor through two numbers per pair that do not depend on g:
+//     P_b = sum_{rows of b, chan, pol} w conj(M) V,    Q_b = sum w |M|^2.
+// Antenna p then needs num_p = sum_{a1(b) = p} g[a2] P_b + sum_{a2(b) = p} g[a1] conj(P_b) and
+// den_p = sum_{a1 = p} |g[a2]|^2 Q_b + sum_{a2 = p} |g[a1]|^2 Q_b. One pass over the
+// visibilities forms (P, Q) (the rows of a pair, one time step each, are found through a list
+// built with the plan); every iteration after that reads only the pairs' (P, Q) through a
+// per-antenna list of pairs, so the iterations cost almost nothing.
 //
 // Peeling. For each source in decreasing |S| (ties in catalogue order): (P, Q) of the current
 // residual against the source's prediction, the iterations from unit gains, then the
-// residual minus g[a1] conj(g[a2]) times the prediction. Everything is enqueued on the
-// caller's stream; the only host work is ordering the catalogue.
+// residual minus g[a1] conj(g[a2]) times the prediction. The subtraction of one source and
+// the (P, Q) of the next share one pass over the residual (read once, written once).
+// Everything is enqueued on the caller's stream; the only host work is ordering the catalogue.
 #include "internal.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 namespace mwg {
@@ -94,57 +97,152 @@ __global__ __launch_bounds__(kBlock) void k_predict(const double *uvw, const dou
     }
 }
 
-// Per-row (P, Q) against a model array or one predicted source. A segment of L lanes (a power
-// of two <= 64) takes one row: lanes stride over its nchan * npol samples, then the segment
-// sums its values by butterfly shuffles (fixed order). Each wave takes 64 / L rows at a time
-// and strides over the rows, so that a wave does a useful amount of work.
-template <bool FROM_SOURCE>
-__global__ __launch_bounds__(kBlock) void k_cal_rows(const float2 *vis, const float2 *model, const double *uvw,
-                                                     const double *kf, const Src *src, const float *weights,
-                                                     int64_t nrow, int nchan, int npol, int L, float4 *pq) {
+// One pass over the visibilities, pair by pair. A segment of L lanes (a power of two <= 64)
+// takes one antenna pair: lanes stride over the channels of each of the pair's rows, a lane
+// loading the npol values of one (row, channel) record at once. Modes:
+//   0: (P, Q) of the pair against a model array (every polarisation);
+//   1: (P, Q) against the source `next` (parallel hands; cross hands of an unpolarised
+//      point source are zero);
+//   2: first add G S e to the parallel hands of the record (the source `sub`, its flux
+//      negated for a removal, times G = g[a1] conj(g[a2])) and write the record back, then
+//      (P, Q) of the updated values against `next`;
+//   3: the update of mode 2 only.
+// The segment sums its lanes' (P, Q) by butterfly shuffles (fixed order). Each wave takes
+// 64 / L pairs at a time and strides over the pairs.
+struct PairArgs {
+    float2 *vis;
+    const float2 *model;
+    const double *uvw, *kf;
+    const Src *sub, *next;
+    const float2 *gains;       // gains of the removed source (modes 2, 3)
+    const uint32_t *pant;      // [npair] a1 | a2 << 16
+    const int32_t *pstart;     // [npair + 1] CSR of each pair's rows
+    const int32_t *prows;      // [nrow]
+    const float *weights;      // [ngroups] or null
+    int64_t npair;
+    int nchan, npol, L;
+    float4 *pq;                // [npair] (Re P, Im P, Q, 0)
+};
+
+template <int NPOL>
+__device__ inline void load_rec(const float2 *src, float2 (&v)[4]) {
+    if constexpr (NPOL == 4) {
+        const float4 x = ((const float4 *)src)[0], y = ((const float4 *)src)[1];
+        v[0] = make_float2(x.x, x.y);
+        v[1] = make_float2(x.z, x.w);
+        v[2] = make_float2(y.x, y.y);
+        v[3] = make_float2(y.z, y.w);
+    } else if constexpr (NPOL == 2) {
+        const float4 x = ((const float4 *)src)[0];
+        v[0] = make_float2(x.x, x.y);
+        v[1] = make_float2(x.z, x.w);
+    } else {
+        v[0] = src[0];
+    }
+}
+
+template <int NPOL>
+__device__ inline void store_rec(float2 *dst, const float2 (&v)[4]) {
+    if constexpr (NPOL == 4) {
+        ((float4 *)dst)[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        ((float4 *)dst)[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    } else if constexpr (NPOL == 2) {
+        ((float4 *)dst)[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    } else {
+        dst[0] = v[0];
+    }
+}
+
+template <int MODE, int NPOL>
+__global__ __launch_bounds__(kBlock) void k_cal_pairs(PairArgs a) {
     const int lane = (int)(threadIdx.x & 63);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int spw = 64 / L, seg = lane / L, sl = lane % L;
-    const int pshift = npol == 4 ? 2 : (npol == 2 ? 1 : 0);
-    const int ne = nchan * npol;
-    Src s{};
-    if constexpr (FROM_SOURCE) s = *src;
-    for (int64_t r0 = wave * spw; r0 < nrow; r0 += nwave * spw) {
-        const int64_t r = r0 + seg;
-        const bool live = r < nrow;
+    const int L = a.L, spw = 64 / L, seg = lane / L, sl = lane % L;
+    constexpr bool SUB = MODE >= 2, MEASURE = MODE <= 2;
+    Src sn{}, ss{};
+    if constexpr (MODE == 1 || MODE == 2) sn = *a.next;
+    if constexpr (SUB) ss = *a.sub;
+    for (int64_t b0 = wave * spw; b0 < a.npair; b0 += nwave * spw) {
+        const int64_t b = b0 + seg;
+        const bool live = b < a.npair;
         float pr = 0.f, pi = 0.f, q = 0.f;
         if (live) {
-            double path = 0.0;
-            if constexpr (FROM_SOURCE) path = uvw[3 * r] * s.l + uvw[3 * r + 1] * s.m + uvw[3 * r + 2] * s.n1;
-            for (int e = sl; e < ne; e += L) {
-                const int c = e >> pshift, p = e & (npol - 1);
-                const int64_t g = r * nchan + c;
-                const float wt = weights ? weights[g] : 1.0f;
-                if (wt == 0.0f) continue;
-                float2 M;
-                if constexpr (FROM_SOURCE) {
-                    const bool cross = npol == 4 && (p == 1 || p == 2);
-                    if (cross) continue;
-                    const float2 ph = turn_phasor(path * kf[c]);
-                    M = make_float2((float)s.flux * ph.x, (float)s.flux * ph.y);
-                } else {
-                    M = model[g * npol + p];
+            float gr = 0.f, gi = 0.f;  // g[a1] conj(g[a2])
+            if constexpr (SUB) {
+                const uint32_t an = a.pant[b];
+                const float2 g1 = a.gains[an & 0xFFFFu], g2 = a.gains[an >> 16];
+                gr = g1.x * g2.x + g1.y * g2.y;
+                gi = g1.y * g2.x - g1.x * g2.y;
+            }
+            const int k1 = a.pstart[b + 1];
+            for (int k = a.pstart[b]; k < k1; k++) {
+                const int64_t r = a.prows[k];
+                double path_s = 0.0, path_n = 0.0;
+                if constexpr (SUB) path_s = a.uvw[3 * r] * ss.l + a.uvw[3 * r + 1] * ss.m + a.uvw[3 * r + 2] * ss.n1;
+                if constexpr (MODE == 1 || MODE == 2)
+                    path_n = a.uvw[3 * r] * sn.l + a.uvw[3 * r + 1] * sn.m + a.uvw[3 * r + 2] * sn.n1;
+                for (int c = sl; c < a.nchan; c += L) {
+                    const int64_t g = r * a.nchan + c;
+                    float2 *rec = a.vis + g * NPOL;
+                    float2 v[4];
+                    load_rec<NPOL>(rec, v);
+                    const double k = a.kf[c];
+                    if constexpr (SUB) {
+                        const float2 e = turn_phasor(path_s * k);
+                        const float sr = (float)ss.flux * e.x, si = (float)ss.flux * e.y;
+                        const float tr = gr * sr - gi * si, ti = gr * si + gi * sr;
+#pragma unroll
+                        for (int p = 0; p < NPOL; p++) {
+                            if (NPOL == 4 && (p == 1 || p == 2)) continue;
+                            v[p].x += tr;
+                            v[p].y += ti;
+                        }
+                        store_rec<NPOL>(rec, v);
+                    }
+                    if constexpr (MEASURE) {
+                        const float wt = a.weights ? a.weights[g] : 1.0f;
+                        if (wt != 0.0f) {
+                            if constexpr (MODE == 0) {
+                                float2 m[4];
+                                load_rec<NPOL>(a.model + g * NPOL, m);
+#pragma unroll
+                                for (int p = 0; p < NPOL; p++) {
+                                    pr += wt * (m[p].x * v[p].x + m[p].y * v[p].y);
+                                    pi += wt * (m[p].x * v[p].y - m[p].y * v[p].x);
+                                    q += wt * (m[p].x * m[p].x + m[p].y * m[p].y);
+                                }
+                            } else {
+                                const float2 e = turn_phasor(path_n * k);
+                                const float mx = (float)sn.flux * e.x, my = (float)sn.flux * e.y;
+#pragma unroll
+                                for (int p = 0; p < NPOL; p++) {
+                                    if (NPOL == 4 && (p == 1 || p == 2)) continue;
+                                    pr += wt * (mx * v[p].x + my * v[p].y);
+                                    pi += wt * (mx * v[p].y - my * v[p].x);
+                                    q += wt * (mx * mx + my * my);
+                                }
+                            }
+                        }
+                    }
                 }
-                const float2 V = vis[g * npol + p];
-                // conj(M) V and |M|^2, weighted
-                pr += wt * (M.x * V.x + M.y * V.y);
-                pi += wt * (M.x * V.y - M.y * V.x);
-                q += wt * (M.x * M.x + M.y * M.y);
             }
         }
-        for (int o = L / 2; o >= 1; o >>= 1) {
-            pr += __shfl_xor(pr, o, 64);
-            pi += __shfl_xor(pi, o, 64);
-            q += __shfl_xor(q, o, 64);
+        if constexpr (MEASURE) {
+            for (int o = L / 2; o >= 1; o >>= 1) {
+                pr += __shfl_xor(pr, o, 64);
+                pi += __shfl_xor(pi, o, 64);
+                q += __shfl_xor(q, o, 64);
+            }
+            if (live && sl == 0) a.pq[b] = make_float4(pr, pi, q, 0.f);
         }
-        if (live && sl == 0) pq[r] = make_float4(pr, pi, q, 0.f);
     }
+}
+
+// f / c of every channel (FP64 division, correctly rounded like the host's)
+__global__ void k_turns_per_metre(const double *freq, int n, double *kf) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) kf[i] = freq[i] / kC;
 }
 
 __global__ void k_fill_gains(float2 *g, int n, float2 v) {
@@ -152,11 +250,11 @@ __global__ void k_fill_gains(float2 *g, int n, float2 v) {
     if (i < n) g[i] = v;
 }
 
-// One StEFCal iteration (number it, from 1): one workgroup per antenna gathers its rows'
+// One StEFCal iteration (number it, from 1): one workgroup per antenna gathers its pairs'
 // (P, Q) (FP64 sums: each thread a strided share of the list, then a fixed-order tree), solves
 // its gain and writes the next iterate (the mean with the previous one on even iterations);
 // diff / nrm receive |g_new - g_old|^2 and |g_new|^2. A whole workgroup per antenna keeps
-// many independent loads of the list in flight (an antenna has thousands of rows).
+// many independent loads of the list in flight.
 __global__ __launch_bounds__(kBlock) void k_cal_ants(const float4 *pq, const int32_t *partner, const int32_t *start,
                                                      const int32_t *entry, int nant, const float2 *gin, float2 *gout,
                                                      int it, double *diff, double *nrm) {
@@ -169,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_cal_ants(const float4 *pq, const int
         const int32_t e = entry[k];
         const float4 v = pq[e >> 1];
         const float2 o = gin[partner[k]];
-        // a1(r) = a: g[a2] P; a2(r) = a: g[a1] conj(P)
+        // a1(b) = a: g[a2] P; a2(b) = a: g[a1] conj(P)
         const double pim = (e & 1) ? -(double)v.y : (double)v.y;
         nr += (double)o.x * v.x - (double)o.y * pim;
         ni += (double)o.x * pim + (double)o.y * v.x;
@@ -247,23 +345,53 @@ int lanes_per_row(int ne) {
     return L;
 }
 
-// Per-row sums, then niter iterations starting from the gains in g (device [nant]); the
-// solution ends in g, the last iteration's relative step in *rel (device) when rel is given.
-Status solve(Instance &I, const float2 *vis, const float2 *model, const Src *src, const float *weights, float2 *g,
-             int niter, float *rel, hipStream_t s) {
-    const int L = lanes_per_row(I.nchan * I.npol);
-    const int64_t waves = (I.nrow + (64 / L) - 1) / (64 / L);
-    // about 16 rounds of rows per wave, at most 2048 workgroups
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (waves + 63) / 64));
-    if (I.nrow > 0) {
-        if (src)
-            hipLaunchKernelGGL(k_cal_rows<true>, dim3(blocks), dim3(kBlock), 0, s, vis, model, I.uvw_d, I.kf_d, src,
-                               weights, I.nrow, I.nchan, I.npol, L, I.cal_pq);
-        else
-            hipLaunchKernelGGL(k_cal_rows<false>, dim3(blocks), dim3(kBlock), 0, s, vis, model, I.uvw_d, I.kf_d, src,
-                               weights, I.nrow, I.nchan, I.npol, L, I.cal_pq);
-        MWG_HIP(hipGetLastError());
+// One pass of k_cal_pairs in the given mode (see there).
+Status cal_pass(Instance &I, int mode, float2 *vis, const float2 *model, const Src *sub, const Src *next,
+                const float2 *gains, const float *weights, hipStream_t s) {
+    if (I.cal_npair == 0) return Status::Ok();
+    PairArgs a;
+    a.vis = vis;
+    a.model = model;
+    a.uvw = I.uvw_d;
+    a.kf = I.kf_d;
+    a.sub = sub;
+    a.next = next;
+    a.gains = gains;
+    a.pant = I.cal_pant;
+    a.pstart = I.cal_pstart;
+    a.prows = I.cal_prows;
+    a.weights = weights;
+    a.npair = I.cal_npair;
+    a.nchan = I.nchan;
+    a.npol = I.npol;
+    a.L = lanes_per_row(I.nchan);
+    a.pq = I.cal_pq;
+    const int64_t waves = (I.cal_npair + (64 / a.L) - 1) / (64 / a.L);
+    // about 4 rounds of pairs per wave, at most 2048 workgroups
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, (waves + 15) / 16));
+#define MWG_PASS(M, NP) hipLaunchKernelGGL((k_cal_pairs<M, NP>), dim3(blocks), dim3(kBlock), 0, s, a)
+#define MWG_PASS_NP(M)                                                                                        \
+    do {                                                                                                      \
+        if (I.npol == 4) MWG_PASS(M, 4);                                                                      \
+        else if (I.npol == 2) MWG_PASS(M, 2);                                                                 \
+        else MWG_PASS(M, 1);                                                                                  \
+    } while (0)
+    switch (mode) {
+    case 0: MWG_PASS_NP(0); break;
+    case 1: MWG_PASS_NP(1); break;
+    case 2: MWG_PASS_NP(2); break;
+    default: MWG_PASS_NP(3); break;
     }
+#undef MWG_PASS_NP
+#undef MWG_PASS
+    MWG_HIP(hipGetLastError());
+    return Status::Ok();
+}
+
+// niter iterations from the gains in g (device [nant]) on the pairs' (P, Q) of the last
+// pass; the solution ends in g, the last iteration's relative step in *rel (device) when
+// rel is given.
+Status iterate(Instance &I, float2 *g, int niter, float *rel, hipStream_t s) {
     // ping-pong between g and the plan's second gain buffer, ending in g
     float2 *bufs[2] = {g, I.cal_g};
     int cur = 0;
@@ -291,8 +419,10 @@ Status solve(Instance &I, const float2 *vis, const float2 *model, const Src *src
 
 Status stage_sources(Instance &I, const double *sources, int nsrc, bool from_host, hipStream_t s);
 
-// Plan-time state of prediction and calibration: device copies of uvw and the frequencies,
-// and (with antennas) the per-antenna list of rows, the per-row sums and the gain buffers.
+// Plan-time state of prediction and calibration: device copies of uvw and f / c, and (with
+// antennas) the antenna pairs: each pair's rows, each antenna's pairs, the per-pair sums and
+// the gain buffers. Pairs are numbered in order of their first row; an antenna's pairs and a
+// pair's rows are listed in ascending order.
 Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_dev, const int32_t *a1_dev,
                          const int32_t *a2_dev, hipStream_t s) {
     void *p;
@@ -300,57 +430,94 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     I.uvw_d = (double *)p;
     if (I.nrow > 0)
         MWG_HIP(hipMemcpyAsync(I.uvw_d, uvw_dev, sizeof(double) * 3 * (size_t)I.nrow, hipMemcpyDeviceToDevice, s));
-    {
-        // turns per metre of every channel, f / c, formed on the host in FP64
-        std::vector<double> kf((size_t)I.nchan);
-        MWG_HIP(hipMemcpyAsync(kf.data(), freq_dev, sizeof(double) * (size_t)I.nchan, hipMemcpyDeviceToHost, s));
-        MWG_HIP(hipStreamSynchronize(s));
-        for (double &f : kf) f = f / kC;
-        MWG_TRY(I.arena.alloc(&p, sizeof(double) * (size_t)I.nchan));
-        I.kf_d = (double *)p;
-        MWG_HIP(hipMemcpyAsync(I.kf_d, kf.data(), sizeof(double) * (size_t)I.nchan, hipMemcpyHostToDevice, s));
-        MWG_HIP(hipStreamSynchronize(s));
-    }
+    MWG_TRY(I.arena.alloc(&p, sizeof(double) * (size_t)std::max(I.nchan, 1)));
+    I.kf_d = (double *)p;
+    hipLaunchKernelGGL(k_turns_per_metre, dim3(grid1d(I.nchan)), dim3(kBlock), 0, s, freq_dev, I.nchan, I.kf_d);
+    MWG_HIP(hipGetLastError());
     if (!I.has_ants) return Status::Ok();
+    if (I.nrow >= (int64_t)1 << 30) return make_error(MW_ERR_UNSUPPORTED, "calibration lists need nrow < 2^30");
     std::vector<int32_t> h1((size_t)I.nrow), h2((size_t)I.nrow);
     if (I.nrow > 0) {
         MWG_HIP(hipMemcpyAsync(h1.data(), a1_dev, 4 * (size_t)I.nrow, hipMemcpyDeviceToHost, s));
         MWG_HIP(hipMemcpyAsync(h2.data(), a2_dev, 4 * (size_t)I.nrow, hipMemcpyDeviceToHost, s));
     }
     MWG_HIP(hipStreamSynchronize(s));
-    // rows of each antenna: entry = row << 1 | (0: as ant1, 1: as ant2), rows ascending
-    std::vector<int32_t> start((size_t)I.nant + 1, 0), entry(2 * (size_t)I.nrow), partner(2 * (size_t)I.nrow);
-    for (int64_t r = 0; r < I.nrow; r++) {
-        start[h1[r] + 1]++;
-        start[h2[r] + 1]++;
+    // pair of every row (a dense table of antenna pairs up to 2048 antennas, else a hash map)
+    std::vector<int32_t> pair_of((size_t)I.nrow);
+    std::vector<uint32_t> pant;
+    {
+        const int64_t nn = (int64_t)I.nant * I.nant;
+        if (nn <= ((int64_t)1 << 22)) {
+            std::vector<int32_t> id((size_t)std::max<int64_t>(nn, 1), -1);
+            for (int64_t r = 0; r < I.nrow; r++) {
+                int32_t &x = id[(size_t)h1[r] * I.nant + h2[r]];
+                if (x < 0) {
+                    x = (int32_t)pant.size();
+                    pant.push_back((uint32_t)h1[r] | (uint32_t)h2[r] << 16);
+                }
+                pair_of[r] = x;
+            }
+        } else {
+            std::unordered_map<uint64_t, int32_t> id;
+            for (int64_t r = 0; r < I.nrow; r++) {
+                auto ins = id.emplace((uint64_t)h1[r] << 32 | (uint32_t)h2[r], (int32_t)pant.size());
+                if (ins.second) pant.push_back((uint32_t)h1[r] | (uint32_t)h2[r] << 16);
+                pair_of[r] = ins.first->second;
+            }
+        }
+    }
+    const int64_t npair = (int64_t)pant.size();
+    I.cal_npair = npair;
+    // rows of each pair
+    std::vector<int32_t> pstart((size_t)npair + 1, 0), prows((size_t)I.nrow);
+    for (int64_t r = 0; r < I.nrow; r++) pstart[pair_of[r] + 1]++;
+    for (int64_t b = 0; b < npair; b++) pstart[b + 1] += pstart[b];
+    {
+        std::vector<int32_t> fill(pstart.begin(), pstart.end() - 1);
+        for (int64_t r = 0; r < I.nrow; r++) prows[fill[pair_of[r]]++] = (int32_t)r;
+    }
+    // pairs of each antenna: entry = pair << 1 | (0: as ant1, 1: as ant2), partner = the other
+    std::vector<int32_t> start((size_t)I.nant + 1, 0), entry(2 * (size_t)npair), partner(2 * (size_t)npair);
+    for (int64_t b = 0; b < npair; b++) {
+        start[(pant[b] & 0xFFFFu) + 1]++;
+        start[(pant[b] >> 16) + 1]++;
     }
     for (int a = 0; a < I.nant; a++) start[a + 1] += start[a];
     {
         std::vector<int32_t> fill(start.begin(), start.end() - 1);
-        for (int64_t r = 0; r < I.nrow; r++) {
-            partner[fill[h1[r]]] = h2[r];
-            entry[fill[h1[r]]++] = (int32_t)(r << 1);
-            partner[fill[h2[r]]] = h1[r];
-            entry[fill[h2[r]]++] = (int32_t)(r << 1 | 1);
+        for (int64_t b = 0; b < npair; b++) {
+            const int a1 = (int)(pant[b] & 0xFFFFu), a2 = (int)(pant[b] >> 16);
+            partner[fill[a1]] = a2;
+            entry[fill[a1]++] = (int32_t)(b << 1);
+            partner[fill[a2]] = a1;
+            entry[fill[a2]++] = (int32_t)(b << 1 | 1);
         }
     }
-    if (I.nrow >= (int64_t)1 << 30) return make_error(MW_ERR_UNSUPPORTED, "calibration lists need nrow < 2^30");
     MWG_TRY(I.arena.alloc(&p, 4 * start.size()));
     I.cal_start = (int32_t *)p;
     MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(entry.size(), 1)));
     I.cal_entry = (int32_t *)p;
     MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(partner.size(), 1)));
     I.cal_partner = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, sizeof(float4) * (size_t)std::max<int64_t>(I.nrow, 1)));
+    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(pant.size(), 1)));
+    I.cal_pant = (uint32_t *)p;
+    MWG_TRY(I.arena.alloc(&p, 4 * pstart.size()));
+    I.cal_pstart = (int32_t *)p;
+    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(prows.size(), 1)));
+    I.cal_prows = (int32_t *)p;
+    MWG_TRY(I.arena.alloc(&p, sizeof(float4) * (size_t)std::max<int64_t>(npair, 1)));
     I.cal_pq = (float4 *)p;
     MWG_TRY(I.arena.alloc(&p, sizeof(float2) * (size_t)I.nant));
     I.cal_g = (float2 *)p;
     MWG_TRY(I.arena.alloc(&p, sizeof(double) * 2 * (size_t)I.nant));
     I.cal_red = (double *)p;
     MWG_HIP(hipMemcpyAsync(I.cal_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice, s));
-    if (!entry.empty()) {
+    MWG_HIP(hipMemcpyAsync(I.cal_pstart, pstart.data(), 4 * pstart.size(), hipMemcpyHostToDevice, s));
+    if (npair > 0) {
         MWG_HIP(hipMemcpyAsync(I.cal_entry, entry.data(), 4 * entry.size(), hipMemcpyHostToDevice, s));
         MWG_HIP(hipMemcpyAsync(I.cal_partner, partner.data(), 4 * partner.size(), hipMemcpyHostToDevice, s));
+        MWG_HIP(hipMemcpyAsync(I.cal_pant, pant.data(), 4 * pant.size(), hipMemcpyHostToDevice, s));
+        MWG_HIP(hipMemcpyAsync(I.cal_prows, prows.data(), 4 * prows.size(), hipMemcpyHostToDevice, s));
     }
     MWG_HIP(hipStreamSynchronize(s));
     return Status::Ok();
@@ -373,7 +540,8 @@ Status launch_solve_gains(Instance &I, const float2 *vis, const float2 *model, c
                           int niter, float *rel, hipStream_t s) {
     if (!I.has_ants) return make_error(MW_ERR_STATE, "gain solving needs an instance planned with antennas");
     if (niter < 0) return make_error(MW_ERR_INVALID_ARG, "niter must be >= 0");
-    return solve(I, vis, model, nullptr, weights, gains, niter, rel, s);
+    MWG_TRY(cal_pass(I, 0, const_cast<float2 *>(vis), model, nullptr, nullptr, nullptr, weights, s));
+    return iterate(I, gains, niter, rel, s);
 }
 
 Status launch_peel(Instance &I, const float2 *vis, const double *sources_host, int nsrc, const float *weights,
@@ -391,15 +559,24 @@ Status launch_peel(Instance &I, const float2 *vis, const double *sources_host, i
     });
     MWG_TRY(stage_sources(I, sources_host, nsrc, true, s));
     const Src *table = (const Src *)I.src_d;  // [2 nsrc]: source k, then its negation at nsrc + k
-    for (int k : order) {
+    // pass i: remove source order[i - 1] with its gains (from the second source on) and form
+    // (P, Q) of order[i]; a last pass removes the last source
+    for (size_t i = 0; i < order.size(); i++) {
+        const int k = order[i];
         float2 *gk = gains + (size_t)k * I.nant;
         hipLaunchKernelGGL(k_fill_gains, dim3(grid1d(I.nant)), dim3(kBlock), 0, s, gk, I.nant, make_float2(1.f, 0.f));
         MWG_HIP(hipGetLastError());
-        MWG_TRY(solve(I, resid, nullptr, table + k, weights, gk, niter, rel ? rel + k : nullptr, s));
-        hipLaunchKernelGGL(k_predict, dim3(grid1d(I.ngroups)), dim3(kBlock), 0, s, I.uvw_d, I.kf_d, I.ngroups,
-                           I.nchan, I.npol, table + nsrc + k, 1, (const float2 *)gk, I.ant_orig, resid, 1);
-        MWG_HIP(hipGetLastError());
+        if (i == 0) {
+            MWG_TRY(cal_pass(I, 1, resid, nullptr, nullptr, table + k, nullptr, weights, s));
+        } else {
+            const int kp = order[i - 1];
+            MWG_TRY(cal_pass(I, 2, resid, nullptr, table + nsrc + kp, table + k, gains + (size_t)kp * I.nant, weights,
+                             s));
+        }
+        MWG_TRY(iterate(I, gk, niter, rel ? rel + k : nullptr, s));
     }
+    const int kl = order.back();
+    MWG_TRY(cal_pass(I, 3, resid, nullptr, table + nsrc + kl, nullptr, gains + (size_t)kl * I.nant, nullptr, s));
     return Status::Ok();
 }
 
