@@ -44,56 +44,80 @@ constexpr int kBlock = 256;
 
 unsigned grid1d(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
-// exp(-2 pi i t) for t in turns (FP64), evaluated after reduction to [-1/2, 1/2] turn
+// exp(-2 pi i t) for t in turns (FP64), after reduction to [-1/2, 1/2] turn, by the hardware
+// sine and cosine, whose input is in turns (over [-1/2, 1/2] turn their largest absolute
+// error, measured against FP64, is 1.3e-7, the size of the rounding of the reduced phase to
+// FP32; the library sincospif reaches 5e-8 at several times the instruction count)
 __device__ inline float2 turn_phasor(double t) {
-    const double fr = t - rint(t);
-    float s, c;
-    sincospif(-2.0f * (float)fr, &s, &c);
-    return make_float2(c, s);
+    const float fr = (float)(t - rint(t));
+    return make_float2(__builtin_amdgcn_cosf(fr), -__builtin_amdgcn_sinf(fr));
 }
 
 struct Src {
     double l, m, n1, flux;  // n1 = sqrt(1 - l^2 - m^2) - 1
 };
 
-// Model visibilities of nsrc point sources (sources in global memory, read through L1), times
-// g[a1] conj(g[a2]) when gains are given; written or added to out [ng][npol]. Cross
-// polarisations (1, 2 of 4) of an unpolarised source are zero. One thread per group.
-__global__ __launch_bounds__(kBlock) void k_predict(const double *uvw, const double *kf, int64_t ng, int nchan,
+// Model visibilities of nsrc point sources (sources in global memory, read as uniform scalar
+// loads), times g[a1] conj(g[a2]) when gains are given; written or added to out [ng][npol].
+// Cross polarisations (1, 2 of 4) of an unpolarised source are zero. One thread per row and
+// run of kPredChan consecutive channels: a source's path length u l + v m + w (n - 1) is
+// formed once for the run, and only its product with each channel's f / c per channel.
+constexpr int kPredChan = 4;
+
+__global__ __launch_bounds__(kBlock) void k_predict(const double *uvw, const double *kf, int64_t nrow, int nchan,
                                                     int npol, const Src *src, int nsrc, const float2 *gains,
                                                     const uint32_t *ants, float2 *out, int accumulate) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
-    const uint32_t r = (uint32_t)g / (uint32_t)nchan;  // ngroups < 2^31
-    const int c = (int)((uint32_t)g - r * (uint32_t)nchan);
-    const double k = kf[c];  // turns per metre, f / c
+    const int nrun = (nchan + kPredChan - 1) / kPredChan;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrow * nrun) return;
+    const int64_t r = t / nrun;
+    const int c0 = (int)(t - r * nrun) * kPredChan;
+    const int nc = min(kPredChan, nchan - c0);
+    double k[kPredChan];
+#pragma unroll
+    for (int q = 0; q < kPredChan; q++) k[q] = kf[c0 + (q < nc ? q : 0)];
     const double u = uvw[3 * r], v = uvw[3 * r + 1], w = uvw[3 * r + 2];
-    float sr = 0.f, si = 0.f;
+    float sr[kPredChan], si[kPredChan];
+#pragma unroll
+    for (int q = 0; q < kPredChan; q++) sr[q] = si[q] = 0.f;
     for (int j = 0; j < nsrc; j++) {
-        const Src q = src[j];
-        const double path = u * q.l + v * q.m + w * q.n1;
-        const float2 e = turn_phasor(path * k);
-        sr += (float)q.flux * e.x;
-        si += (float)q.flux * e.y;
+        const Src s = src[j];
+        const double path = u * s.l + v * s.m + w * s.n1;
+        const float flux = (float)s.flux;
+#pragma unroll
+        for (int q = 0; q < kPredChan; q++) {
+            const float2 e = turn_phasor(path * k[q]);
+            sr[q] += flux * e.x;
+            si[q] += flux * e.y;
+        }
     }
+    float gr = 1.f, gi = 0.f;  // g1 conj(g2)
     if (gains) {
         const uint32_t an = ants[r];
         const float2 g1 = gains[an & 0xFFFFu], g2 = gains[an >> 16];
-        const float gr = g1.x * g2.x + g1.y * g2.y, gi = g1.y * g2.x - g1.x * g2.y;  // g1 conj(g2)
-        const float tr = gr * sr - gi * si, ti = gr * si + gi * sr;
-        sr = tr;
-        si = ti;
+        gr = g1.x * g2.x + g1.y * g2.y;
+        gi = g1.y * g2.x - g1.x * g2.y;
     }
-    float2 *o = out + g * npol;
-    for (int p = 0; p < npol; p++) {
-        const bool cross = npol == 4 && (p == 1 || p == 2);
-        float2 val = cross ? make_float2(0.f, 0.f) : make_float2(sr, si);
-        if (accumulate) {
-            const float2 old = o[p];
-            val.x += old.x;
-            val.y += old.y;
+#pragma unroll
+    for (int q = 0; q < kPredChan; q++) {
+        if (q >= nc) break;
+        float mr = sr[q], mi = si[q];
+        if (gains) {
+            const float tr = gr * mr - gi * mi, ti = gr * mi + gi * mr;
+            mr = tr;
+            mi = ti;
         }
-        o[p] = val;
+        float2 *o = out + (r * nchan + c0 + q) * npol;
+        for (int p = 0; p < npol; p++) {
+            const bool cross = npol == 4 && (p == 1 || p == 2);
+            float2 val = cross ? make_float2(0.f, 0.f) : make_float2(mr, mi);
+            if (accumulate) {
+                const float2 old = o[p];
+                val.x += old.x;
+                val.y += old.y;
+            }
+            o[p] = val;
+        }
     }
 }
 
@@ -530,7 +554,8 @@ Status launch_predict(Instance &I, const double *sources, int nsrc, const float2
     if (gains && !I.has_ants) return make_error(MW_ERR_STATE, "gains given for an instance planned without antennas");
     // the source table as (l, m, n - 1, S) in the plan's device buffer
     MWG_TRY(stage_sources(I, sources, nsrc, false, s));
-    hipLaunchKernelGGL(k_predict, dim3(grid1d(I.ngroups)), dim3(kBlock), 0, s, I.uvw_d, I.kf_d, I.ngroups, I.nchan,
+    const int64_t nthreads = I.nrow * ((I.nchan + kPredChan - 1) / kPredChan);
+    hipLaunchKernelGGL(k_predict, dim3(grid1d(nthreads)), dim3(kBlock), 0, s, I.uvw_d, I.kf_d, I.nrow, I.nchan,
                        I.npol, (const Src *)I.src_d, nsrc, gains, I.ant_orig, out, accumulate);
     MWG_HIP(hipGetLastError());
     return Status::Ok();

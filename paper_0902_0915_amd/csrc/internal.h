@@ -178,7 +178,9 @@ struct Instance {
     size_t cap_pairs = 0, cap_owork = 0, cap_ozero = 0;
     // host copies of the lists built on the host (the batched plan reads them back from here)
     std::vector<WorkItem> h_work, h_owork;
-    std::vector<int32_t> h_mblocks, h_ozero;
+    std::vector<int32_t> h_mblocks, h_ozero, h_tw, h_ids;
+    std::vector<int2> h_coop;
+    std::vector<float> h_taps2d, h_tabpad, h_tab8;  // sources of the table uploads
     float *partial = nullptr;     // merge flush scratch: [nwork][R*R][2*npol] (cell-major)
     size_t partial_bytes = 0;
     float *taps2d = nullptr;      // [O*O][64] separable taps products (W <= 7 lanes layout)

@@ -214,16 +214,17 @@ Status build_owner_schedule(Instance &I, int64_t cap, bool *built, hipStream_t s
                            I.sant ? I.psant : nullptr);
         MWG_HIP(hipGetLastError());
     }
-    if (!items.empty())
-        MWG_HIP(hipMemcpyAsync(I.owork, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s));
-    if (!zero.empty())
-        MWG_HIP(hipMemcpyAsync(I.ozero, zero.data(), 4 * zero.size(), hipMemcpyHostToDevice, s));
-    MWG_HIP(hipStreamSynchronize(s));
+    // the host lists stay in the instance (the uploads are not waited for here)
+    I.h_owork.swap(items);
+    I.h_ozero.swap(zero);
+    if (!I.h_owork.empty())
+        MWG_HIP(hipMemcpyAsync(I.owork, I.h_owork.data(), sizeof(WorkItem) * I.h_owork.size(), hipMemcpyHostToDevice,
+                               s));
+    if (!I.h_ozero.empty())
+        MWG_HIP(hipMemcpyAsync(I.ozero, I.h_ozero.data(), 4 * I.h_ozero.size(), hipMemcpyHostToDevice, s));
     I.owner_tile = T;
-    I.nowork = (int)items.size();
-    I.n_ozero = (int)zero.size();
-    I.h_owork = items;
-    I.h_ozero = zero;
+    I.nowork = (int)I.h_owork.size();
+    I.n_ozero = (int)I.h_ozero.size();
     I.max_owner_groups = maxn;
     I.npairs_owner = npairs;
     *built = true;

@@ -763,7 +763,8 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     // (at most wg_waves) consecutive waves of one workgroup, wave j taking the j-th of nsub
     // equal parts. Items are in largest-first order, so nsub never grows along the list and
     // the items pack the workgroups' wave slots without gaps (only the last one is padded).
-    std::vector<int2> coop;
+    std::vector<int2> &coop = I.h_coop;
+    coop.clear();
     if (L.schedule == 3) {
         const int nw = L.wg_waves;
         const int64_t per = std::max(64, L.split / nw);
@@ -777,7 +778,9 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         if (coop.size() % nw) coop.resize((coop.size() / nw + 1) * nw, make_int2(-1, 0));
     }
     // CSR of work items per tile (for the deterministic merge flush)
-    std::vector<int32_t> tw(ntiles + 1, 0), ids(items.size());
+    std::vector<int32_t> &tw = I.h_tw, &ids = I.h_ids;
+    tw.assign((size_t)ntiles + 1, 0);
+    ids.assign(items.size(), 0);
     for (const WorkItem &w : items) tw[w.tile + 1]++;
     for (int64_t t = 0; t < ntiles; t++) tw[t + 1] += tw[t];
     {
@@ -785,7 +788,8 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         for (size_t i = 0; i < items.size(); i++) ids[fillp[items[i].tile]++] = (int32_t)i;
     }
     // Merge blocks that some work item's haloed tile reaches, then those none reaches.
-    std::vector<int32_t> mlist;
+    std::vector<int32_t> &mlist = I.h_mblocks;
+    mlist.clear();
     int nmerge = 0;
     {
         // a block is reached when it meets the haloed extent [tx T - h, tx T + T - 1 + h] of
@@ -808,17 +812,20 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         for (int b = 0; b < bpr * bpc; b++)
             if (!reach[b]) mlist.push_back(b);
     }
-    // (re)allocate schedule arrays: these are small; keep them in the arena
+    // (re)allocate schedule arrays: these are small; keep them in the arena. The host lists
+    // stay in the instance (the batched plan reads them, and the uploads are not waited for).
+    I.h_work.swap(items);
+    const std::vector<WorkItem> &work_list = I.h_work;
     I.L = L;
     I.ntx = ntx;
     I.nty = nty;
     I.ntiles_nonempty = nonempty;
-    I.nwork = (int)items.size();
+    I.nwork = (int)work_list.size();
     I.max_work_groups = 0;
-    for (const WorkItem &w : items) I.max_work_groups = std::max(I.max_work_groups, w.end - w.begin);
+    for (const WorkItem &w : work_list) I.max_work_groups = std::max(I.max_work_groups, w.end - w.begin);
     void *p;
-    if (I.cap_work < std::max<size_t>(items.size(), 1)) {
-        I.cap_work = std::max<size_t>(items.size(), 1);
+    if (I.cap_work < std::max<size_t>(work_list.size(), 1)) {
+        I.cap_work = std::max<size_t>(work_list.size(), 1);
         MWG_TRY(I.arena.alloc(&p, sizeof(WorkItem) * I.cap_work));
         I.work = (WorkItem *)p;
         MWG_TRY(I.arena.alloc(&p, 4 * I.cap_work));
@@ -829,8 +836,8 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         MWG_TRY(I.arena.alloc(&p, 4 * I.cap_tiles));
         I.tile_work = (int32_t *)p;
     }
-    if (!items.empty())
-        MWG_HIP(hipMemcpyAsync(I.work, items.data(), sizeof(WorkItem) * items.size(),
+    if (!work_list.empty())
+        MWG_HIP(hipMemcpyAsync(I.work, work_list.data(), sizeof(WorkItem) * work_list.size(),
                                hipMemcpyHostToDevice, s));
     I.coop_wgs = L.schedule == 3 ? (int)(coop.size() / L.wg_waves) : 0;
     if (!coop.empty()) {
@@ -851,8 +858,7 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
     MWG_HIP(hipMemcpyAsync(I.mblocks, mlist.data(), 4 * mlist.size(), hipMemcpyHostToDevice, s));
     I.n_mblocks = nmerge;
     I.n_zblocks = (int)mlist.size() - nmerge;
-    I.h_work = items;
-    I.h_mblocks = mlist;
+
     // Sorted per-group arrays follow the new permutation.
     if (nk > 0) {
         if (resort) {
@@ -867,7 +873,6 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
             MWG_HIP(hipGetLastError());
         }
     }
-    MWG_HIP(hipStreamSynchronize(s));
     if (L.flush == 3) {
         bool built = false;
         MWG_TRY(build_owner_schedule(I, 0, &built, s));
@@ -1009,24 +1014,24 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     MWG_TRY(stage_input(d.ant1, (size_t)d.nrow, d.mem, t_a1, &a1, s));
     MWG_TRY(stage_input(d.ant2, (size_t)d.nrow, d.mem, t_a2, &a2, s));
     void *p;
-    // Index arrays must stay inside the arrays they index (checked once, on the device).
-    {
-        Tmp bad;
-        MWG_TRY(bad.alloc(sizeof(unsigned long long), s));
-        MWG_TRY(launch_fill_u32(bad.as<uint32_t>(), 2, 0, s));
-        if (a1 && d.nrow > 0) {
-            hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a1,
-                               (int64_t)d.nrow, d.nant, bad.as<unsigned long long>());
-            hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a2,
-                               (int64_t)d.nrow, d.nant, bad.as<unsigned long long>());
-            MWG_HIP(hipGetLastError());
-        }
-        if (I.stacks && ng > 0) {
-            MWG_TRY(stage_input(d.kernel_index, (size_t)ng, d.mem, t_kidx, &kidx, s));
-            hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(ng)), dim3(kBlock), 0, s, kidx, ng,
-                               d.nkernel, bad.as<unsigned long long>());
-            MWG_HIP(hipGetLastError());
-        }
+    // Index arrays must stay inside the arrays they index (counted on the device). Kernel
+    // indices are checked before the positions pass reads through them; antenna indices
+    // together with the positions counts (nothing reads through them before that).
+    Tmp bad;
+    MWG_TRY(bad.alloc(sizeof(unsigned long long), s));
+    MWG_TRY(launch_fill_u32(bad.as<uint32_t>(), 2, 0, s));
+    if (a1 && d.nrow > 0) {
+        hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a1, (int64_t)d.nrow,
+                           d.nant, bad.as<unsigned long long>());
+        hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(d.nrow)), dim3(kBlock), 0, s, a2, (int64_t)d.nrow,
+                           d.nant, bad.as<unsigned long long>());
+        MWG_HIP(hipGetLastError());
+    }
+    if (I.stacks && ng > 0) {
+        MWG_TRY(stage_input(d.kernel_index, (size_t)ng, d.mem, t_kidx, &kidx, s));
+        hipLaunchKernelGGL(k_count_out_of_range, dim3(grid1d(ng)), dim3(kBlock), 0, s, kidx, ng, d.nkernel,
+                           bad.as<unsigned long long>());
+        MWG_HIP(hipGetLastError());
         unsigned long long hb = 0;
         MWG_HIP(hipMemcpyAsync(&hb, bad.p, sizeof hb, hipMemcpyDeviceToHost, s));
         MWG_HIP(hipStreamSynchronize(s));
@@ -1118,8 +1123,11 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         MWG_HIP(hipGetLastError());
         MWG_HIP(hipMemcpyAsync(&h8, tiles8.p, sizeof h8, hipMemcpyDeviceToHost, s));
     }
+    unsigned long long hbad = 0;
+    MWG_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof hbad, hipMemcpyDeviceToHost, s));
     MWG_HIP(hipMemcpyAsync(hc, counts.p, sizeof hc, hipMemcpyDeviceToHost, s));
     MWG_HIP(hipStreamSynchronize(s));
+    if (hbad) return make_error(MW_ERR_INVALID_ARG, "%llu antenna or kernel indices out of range", hbad);
     I.nkept = (int64_t)hc[0];
     I.nflagged = (int64_t)hc[1];
     I.noutside = (int64_t)hc[2];
@@ -1188,7 +1196,9 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     // A3: kernel tables (built-in kernel) and correction vectors
     if (!I.stacks) {
         prolate_tables(I.W, I.O, I.nx, I.ny, I.h_tab, I.h_corrx, I.h_corry);
-        std::vector<float> taps2d((size_t)I.O * I.O * 64, 0.0f);
+        // (host copies stay in the instance: the uploads below are not waited for here)
+        std::vector<float> &taps2d = I.h_taps2d;
+        taps2d.assign((size_t)I.O * I.O * 64, 0.0f);
         if (I.W * I.W <= 64) {
             for (int py = 0; py < I.O; py++)
                 for (int px = 0; px < I.O; px++)
@@ -1200,12 +1210,14 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         MWG_TRY(I.arena.alloc(&p, 4 * taps2d.size()));
         I.taps2d = (float *)p;
         MWG_HIP(hipMemcpyAsync(I.taps2d, taps2d.data(), 4 * taps2d.size(), hipMemcpyHostToDevice, s));
-        std::vector<float> tabpad(I.h_tab);
+        std::vector<float> &tabpad = I.h_tabpad;
+        tabpad = I.h_tab;
         tabpad.resize(I.h_tab.size() + 8, 0.0f);  // uniform 8-float row reads past the last row
         MWG_TRY(I.arena.alloc(&p, 4 * tabpad.size()));
         I.tab = (float *)p;
         MWG_HIP(hipMemcpyAsync(I.tab, tabpad.data(), 4 * tabpad.size(), hipMemcpyHostToDevice, s));
-        std::vector<float> tab8((size_t)I.O * 8, 0.0f);
+        std::vector<float> &tab8 = I.h_tab8;
+        tab8.assign((size_t)I.O * 8, 0.0f);
         for (int r = 0; r < I.O; r++)
             for (int t = 0; t < I.W && t < 8; t++) tab8[(size_t)r * 8 + t] = I.h_tab[(size_t)r * I.W + t];
         MWG_TRY(I.arena.alloc(&p, 4 * tab8.size()));
@@ -1218,7 +1230,6 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
         I.corry = (float *)p;
         MWG_HIP(hipMemcpyAsync(I.corry, I.h_corry.data(), 4 * (size_t)I.ny, hipMemcpyHostToDevice, s));
     }
-    MWG_HIP(hipStreamSynchronize(s));
     return Status::Ok();
 }
 
