@@ -208,9 +208,10 @@ mw_status mw_grid_noalloc(mw_plan plan, const void *const *vis, const void *cons
  * real loss with respect to the gains of the forward model w * g1 * conj(g2) * V, given that
  * grid[i] holds the gradient with respect to the grid (torch convention dL/dRe + i dL/dIm):
  *   grad_g[a] = sum_{ant1 = a} g2 conj(V) y + sum_{ant2 = a} g1 V conj(y),
- * with y the adjoint output without gains and V = vis_in[i] (required then).
- * Errors: MW_ERR_INVALID_ARG, MW_ERR_STATE (gains for an instance without antennas),
- * MW_ERR_HIP.
+ * with y the adjoint output without gains and V = vis_in[i] (required then). vis_out and
+ * vis_in are 16-byte aligned with 2 or 4 polarisations (8-byte with one), like vis in mw_grid.
+ * Errors: MW_ERR_INVALID_ARG (null or misaligned arrays), MW_ERR_STATE (gains for an
+ * instance without antennas), MW_ERR_HIP.
  */
 mw_status mw_degrid(mw_plan plan, const void *const *grid, const void *const *gains,
                     const void *const *vis_in, void *const *vis_out, void *const *grad_gains,

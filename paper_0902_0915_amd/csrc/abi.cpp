@@ -19,6 +19,9 @@
 constexpr size_t kScratchBytes = size_t(192) << 20;
 static __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
 
+// Plans of at least this many instances build them on parallel host threads.
+constexpr int kParallelPlan = 4;
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -190,10 +193,18 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
         // a plan of several instances settles its tile size across them before sorting any
         const bool autotune = tuning && tuning->autotune;
         const bool defer = ninst > 1 && !autotune;
-        for (int i = 0; i < ninst; i++) {
-            mwg::Instance *I = new mwg::Instance();
-            P->inst.push_back(I);
-            mwg::Status s = mwg::build_instance(*I, inst[i], tuning, st, !defer, ninst > 1);
+        for (int i = 0; i < ninst; i++) P->inst.push_back(new mwg::Instance());
+        {
+            // instances are independent: plans of several are built by parallel host threads
+            auto build = [&](int i, hipStream_t s) {
+                return mwg::build_instance(*P->inst[i], inst[i], tuning, s, !defer, ninst > 1);
+            };
+            mwg::Status s;
+            if (ninst >= kParallelPlan) {
+                s = mwg::parallel_instances(P->device, ninst, st, build);
+            } else {
+                for (int i = 0; i < ninst && s.ok(); i++) s = build(i, st);
+            }
             if (!s.ok()) {
                 destroy_plan(P);
                 return fail(s);
@@ -313,6 +324,10 @@ mw_status mw_degrid(mw_plan plan, const void *const *grid, const void *const *ga
                 return fail(MW_ERR_STATE, "gains or grad_gains for an instance planned without antennas");
             if (gg && (!g || !vis_in || !vis_in[i]))
                 return fail(MW_ERR_INVALID_ARG, "grad_gains needs gains and vis_in");
+            const uintptr_t align = I.npol >= 2 ? 16 : 8;
+            if (((uintptr_t)vis_out[i] % align) || (vis_in && ((uintptr_t)vis_in[i] % align)))
+                return fail(mwg::make_error(MW_ERR_INVALID_ARG, "vis_out[i] and vis_in[i] must be %d-byte aligned",
+                                            (int)align));
         }
         hipStream_t st = (hipStream_t)stream;
         if (n > 1 && P->batch) {

@@ -244,7 +244,7 @@ __global__ void k_degrid_prologue(const BatchDesc *desc, const int64_t *start, i
     }
 }
 
-template <int NPOL>
+template <int NPOL, int WT>
 __global__ __launch_bounds__(256) void k_degrid_batched(const BatchDesc *desc, const BatchItem *items,
                                                         int T, int W, int O, int ant_in_lds) {
     extern __shared__ __align__(16) float smem[];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void k_degrid_batched(const BatchDesc *desc, c
     a.O = O;
     a.nant = d.nant;
     a.ant_in_lds = ant_in_lds;
-    degrid_item<NPOL>(a, d.work[it.item], smem);
+    degrid_item<NPOL, WT>(a, d.work[it.item], smem);
 }
 
 int plane2(int R, int STR, int W) {
@@ -339,8 +339,25 @@ Status enqueue_degrid(Batch &B, int64_t ndrop_total, hipStream_t s) {
         MWG_HIP(hipGetLastError());
     }
     if (B.nditems > 0) {
-        hipLaunchKernelGGL(k_degrid_batched<NPOL>, dim3(B.nditems), dim3(B.dthreads), B.degrid_lds, s, B.d_desc,
-                           B.d_ditems, B.T, B.W, B.O, B.ant_in_lds);
+        const dim3 grid((unsigned)B.nditems), block((unsigned)B.dthreads);
+        switch (B.W) {  // the common supports with their taps in registers
+        case 3:
+            hipLaunchKernelGGL((k_degrid_batched<NPOL, 3>), grid, block, B.degrid_lds, s, B.d_desc, B.d_ditems, B.T,
+                               B.W, B.O, B.ant_in_lds);
+            break;
+        case 5:
+            hipLaunchKernelGGL((k_degrid_batched<NPOL, 5>), grid, block, B.degrid_lds, s, B.d_desc, B.d_ditems, B.T,
+                               B.W, B.O, B.ant_in_lds);
+            break;
+        case 7:
+            hipLaunchKernelGGL((k_degrid_batched<NPOL, 7>), grid, block, B.degrid_lds, s, B.d_desc, B.d_ditems, B.T,
+                               B.W, B.O, B.ant_in_lds);
+            break;
+        default:
+            hipLaunchKernelGGL((k_degrid_batched<NPOL, 0>), grid, block, B.degrid_lds, s, B.d_desc, B.d_ditems, B.T,
+                               B.W, B.O, B.ant_in_lds);
+            break;
+        }
         MWG_HIP(hipGetLastError());
     }
     return Status::Ok();
@@ -410,14 +427,16 @@ Status refresh_desc(Batch &B, const void *const *vis, const void *const *gains, 
 // (variant 4, merge flush, same tile and waves); other plans run instance by instance.
 Status batch_prepare(Plan &P, hipStream_t s) {
     P.batch = nullptr;
+    const int n = (int)P.inst.size();
     // Sparse batches (fewer than 64 kept groups per occupied 8 x 8 tile on average) take
     // 16 x 16 tiles: a quarter of the work items, each staging and flushing less halo per
     // group. The batch as a whole still has items enough to fill the chip, which one sparse
     // instance on its own does not, so single-instance plans keep 8 x 8. The choice needs only
     // the occupied-tile counts of the positions pass, so an instance whose schedule was
     // deferred is sorted once, at its final tile.
+    std::vector<Launch> Ls((size_t)n);
     {
-        bool retile = P.inst.size() >= 2;
+        bool retile = n >= 2;
         int64_t kept = 0, tiles = 0;
         for (const Instance *I : P.inst) {
             retile = retile && !I->stacks && !I->tile_fixed && I->L.variant == 4 && I->L.flush == 2 &&
@@ -427,30 +446,42 @@ Status batch_prepare(Plan &P, hipStream_t s) {
             tiles += I->ntiles8;
         }
         retile = retile && tiles > 0 && kept < 64 * tiles;
-        for (Instance *I : P.inst) {
-            Launch L = I->L;
-            if (retile) L.tile = 16;
-            if (!I->scheduled || L.tile != I->L.tile) MWG_TRY(schedule_instance(*I, L, s));
+        for (int i = 0; i < n; i++) {
+            Ls[(size_t)i] = P.inst[(size_t)i]->L;
+            if (retile) Ls[(size_t)i].tile = 16;
         }
     }
-    if (P.inst.size() < 2) return Status::Ok();
-    const Instance &I0 = *P.inst[0];
-    for (const Instance *I : P.inst) {
-        if (I->stacks || I->npol != I0.npol || I->W != I0.W || I->O != I0.O || I->L.variant != 4 ||
-            (I->L.flush != 2 && I->L.flush != 3) || I->L.schedule != 1 || I->L.tile != I0.L.tile ||
-            I->L.wg_waves != I0.L.wg_waves)
+    // The batched form serves instances that share npol, W, O and the wave-tile launch.
+    bool batchable = n >= 2;
+    for (int i = 0; i < n && batchable; i++) {
+        const Instance &I = *P.inst[(size_t)i], &I0 = *P.inst[0];
+        const Launch &L = Ls[(size_t)i], &L0 = Ls[0];
+        batchable = !I.stacks && I.npol == I0.npol && I.W == I0.W && I.O == I0.O && L.variant == 4 &&
+                    (L.flush == 2 || L.flush == 3) && L.schedule == 1 && L.tile == L0.tile &&
+                    L.wg_waves == L0.wg_waves;
+    }
+    // Per instance (in parallel for many): the schedule at its final launch, then, in a batch,
+    // the owner-tile flush for instances whose output tiles each receive at most kOwnerCap
+    // groups (every cell written once, no scratch tiles, no merge; denser ones keep the merge).
+    auto prepare = [&](int i, hipStream_t ws) -> Status {
+        Instance &I = *P.inst[(size_t)i];
+        const Launch &L = Ls[(size_t)i];
+        if (!I.scheduled || L.tile != I.L.tile) MWG_TRY(schedule_instance(I, L, ws));
+        if (!batchable || I.L.flush != 2 || I.flush_fixed || I.L.tile < I.W - 1 ||
+            owner_lds(I.npol, I.L.tile, I.W, I.O, I.L.wg_waves) > 160 * 1024)
             return Status::Ok();
-    }
-    // Instances whose output tiles each receive at most kOwnerCap groups take the owner-tile
-    // flush: every cell written once, no scratch tiles, no merge. Denser ones keep the merge.
-    for (Instance *I : P.inst) {
-        if (I->L.flush != 2 || I->flush_fixed || I->L.tile < I->W - 1 ||
-            owner_lds(I->npol, I->L.tile, I->W, I->O, I->L.wg_waves) > 160 * 1024)
-            continue;
         bool built = false;
-        MWG_TRY(build_owner_schedule(*I, kOwnerCap, &built, s));
-        if (built) I->L.flush = 3;
+        MWG_TRY(build_owner_schedule(I, kOwnerCap, &built, ws));
+        if (built) I.L.flush = 3;
+        return Status::Ok();
+    };
+    if (n >= 4) {
+        MWG_TRY(parallel_instances(P.device, n, s, prepare));
+    } else {
+        for (int i = 0; i < n; i++) MWG_TRY(prepare(i, s));
     }
+    if (!batchable) return Status::Ok();
+    const Instance &I0 = *P.inst[0];
     Batch *B = new Batch();
     P.batch = B;
     B->ninst = (int)P.inst.size();

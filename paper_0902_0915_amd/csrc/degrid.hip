@@ -21,10 +21,10 @@ Status launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
 namespace {
 
-template <int NPOL>
+template <int NPOL, int WT>
 __global__ __launch_bounds__(1024) void k_degrid(DegridArgs a) {
     extern __shared__ __align__(16) float smem[];
-    degrid_item<NPOL>(a, a.work[blockIdx.x], smem);
+    degrid_item<NPOL, WT>(a, a.work[blockIdx.x], smem);
 }
 
 template <int NPOL>
@@ -54,7 +54,13 @@ Status launch_degrid_npol(Instance &I, DegridArgs &a, hipStream_t s) {
         lds += sizeof(float2) * (size_t)I.nant;
     }
     if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "degrid tile needs %zu B of LDS", lds);
-    hipLaunchKernelGGL(k_degrid<NPOL>, dim3(I.nwork), dim3(degrid_threads(I.nkept, I.nwork)), lds, s, a);
+    const dim3 grid((unsigned)I.nwork), block((unsigned)degrid_threads(I.nkept, I.nwork));
+    switch (I.W) {  // the common supports with their taps in registers
+    case 3: hipLaunchKernelGGL((k_degrid<NPOL, 3>), grid, block, lds, s, a); break;
+    case 5: hipLaunchKernelGGL((k_degrid<NPOL, 5>), grid, block, lds, s, a); break;
+    case 7: hipLaunchKernelGGL((k_degrid<NPOL, 7>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((k_degrid<NPOL, 0>), grid, block, lds, s, a); break;
+    }
     MWG_HIP(hipGetLastError());
     return Status::Ok();
 }

@@ -23,12 +23,104 @@ inline int degrid_threads(int64_t groups, int64_t items) {
     return avg <= 64 ? 64 : (avg <= 128 ? 128 : 256);
 }
 
-// One workgroup grids-back one work item: stage its haloed grid tile in LDS, then one
-// thread per group gathers the footprint. smem is the workgroup's dynamic LDS.
+// A group's footprint sum y[p] = sum_s T[py][s] sum_t T[px][t] G[p][row s][col t] from the
+// LDS tile g (row stride R, planes of R * R) at offset o: each row's sum over t first, then
+// the row tap. With the support a compile-time WT the column taps stay in registers and the
+// window loads pair up; WT = 0 takes the support at run time (any W <= 15).
+template <int NPOL, int WT>
+__device__ inline void degrid_footprint(const float2 *g, const float *tab, int R, int Wrt, int o, int px, int py,
+                                        float2 (&acc)[NPOL]) {
+#pragma unroll
+    for (int p = 0; p < NPOL; p++) acc[p] = make_float2(0.f, 0.f);
+    if constexpr (WT > 0) {
+        float tx[WT];
+#pragma unroll
+        for (int t = 0; t < WT; t++) tx[t] = tab[px * WT + t];
+        // rows one at a time (unrolling them too hoists every window load and spills)
+#pragma unroll 1
+        for (int sy = 0; sy < WT; sy++) {
+            const float ty = tab[py * WT + sy];
+            const float2 *row = g + o + sy * R;
+            float2 rs[NPOL];
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) rs[p] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int sx = 0; sx < WT; sx++) {
+#pragma unroll
+                for (int p = 0; p < NPOL; p++) {
+                    const float2 v = row[(size_t)p * R * R + sx];
+                    rs[p].x = fmaf(tx[sx], v.x, rs[p].x);
+                    rs[p].y = fmaf(tx[sx], v.y, rs[p].y);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                acc[p].x = fmaf(ty, rs[p].x, acc[p].x);
+                acc[p].y = fmaf(ty, rs[p].y, acc[p].y);
+            }
+        }
+    } else {
+        for (int sy = 0; sy < Wrt; sy++) {
+            const float ty = tab[py * Wrt + sy];
+            const float2 *row = g + o + sy * R;
+            float2 rs[NPOL];
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) rs[p] = make_float2(0.f, 0.f);
+            for (int sx = 0; sx < Wrt; sx++) {
+                const float tx = tab[px * Wrt + sx];
+#pragma unroll
+                for (int p = 0; p < NPOL; p++) {
+                    const float2 v = row[(size_t)p * R * R + sx];
+                    rs[p].x = fmaf(tx, v.x, rs[p].x);
+                    rs[p].y = fmaf(tx, v.y, rs[p].y);
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                acc[p].x = fmaf(ty, rs[p].x, acc[p].x);
+                acc[p].y = fmaf(ty, rs[p].y, acc[p].y);
+            }
+        }
+    }
+}
+
+// NPOL complex values of one group's record (16-byte aligned for NPOL >= 2) in one or two
+// vector accesses.
 template <int NPOL>
+__device__ inline void load_record(const float2 *src, float2 (&v)[NPOL]) {
+    if constexpr (NPOL == 4) {
+        const float4 x = ((const float4 *)src)[0], y = ((const float4 *)src)[1];
+        v[0] = make_float2(x.x, x.y);
+        v[1] = make_float2(x.z, x.w);
+        v[2] = make_float2(y.x, y.y);
+        v[3] = make_float2(y.z, y.w);
+    } else if constexpr (NPOL == 2) {
+        const float4 x = ((const float4 *)src)[0];
+        v[0] = make_float2(x.x, x.y);
+        v[1] = make_float2(x.z, x.w);
+    } else {
+        v[0] = src[0];
+    }
+}
+template <int NPOL>
+__device__ inline void store_record(float2 *dst, const float2 (&v)[NPOL]) {
+    if constexpr (NPOL == 4) {
+        ((float4 *)dst)[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        ((float4 *)dst)[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    } else if constexpr (NPOL == 2) {
+        ((float4 *)dst)[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    } else {
+        dst[0] = v[0];
+    }
+}
+
+// One workgroup grids-back one work item: stage its haloed grid tile in LDS, then one
+// thread per group gathers the footprint. smem is the workgroup's dynamic LDS. WT: the
+// support as a compile-time constant (0: a.W at run time).
+template <int NPOL, int WT>
 __device__ inline void degrid_item(const DegridArgs &a, const WorkItem wk, float *smem) {
     const int nthreads = blockDim.x, tid = threadIdx.x;
-    const int T = a.T, W = a.W, h = (W - 1) / 2, R = T + W - 1;
+    const int T = a.T, W = WT > 0 ? WT : a.W, h = (W - 1) / 2, R = T + W - 1;
     const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
     float2 *g = (float2 *)smem;                      // [NPOL][R][R]
     float *tab = (float *)(g + (size_t)NPOL * R * R); // [O][W]
@@ -52,21 +144,7 @@ __device__ inline void degrid_item(const DegridArgs &a, const WorkItem wk, float
         const int px = (int)((pp >> 24) & 0xFu), py = (int)(pp >> 28);
         const int o = (cy - ty0) * R + (cx - tx0);
         float2 acc[NPOL];
-#pragma unroll
-        for (int p = 0; p < NPOL; p++) acc[p] = make_float2(0.f, 0.f);
-        for (int sy = 0; sy < W; sy++) {
-            const float ty = tab[py * W + sy];
-            const float2 *row = g + o + sy * R;
-            for (int sx = 0; sx < W; sx++) {
-                const float tap = ty * tab[px * W + sx];
-#pragma unroll
-                for (int p = 0; p < NPOL; p++) {
-                    const float2 v = row[(size_t)p * R * R + sx];
-                    acc[p].x = fmaf(tap, v.x, acc[p].x);
-                    acc[p].y = fmaf(tap, v.y, acc[p].y);
-                }
-            }
-        }
+        degrid_footprint<NPOL, WT>(g, tab, R, W, o, px, py, acc);
         const float w = a.sw ? a.sw[i] : 1.0f;
 #pragma unroll
         for (int p = 0; p < NPOL; p++) {
@@ -86,7 +164,8 @@ __device__ inline void degrid_item(const DegridArgs &a, const WorkItem wk, float
                 out[p] = make_float2(mr * acc[p].x - mi * acc[p].y, mr * acc[p].y + mi * acc[p].x);
             if (want_g) {
                 float2 t1 = make_float2(0.f, 0.f), t2 = make_float2(0.f, 0.f);
-                const float2 *vin = a.vis_in + (int64_t)gi * NPOL;
+                float2 vin[NPOL];
+                load_record<NPOL>(a.vis_in + (int64_t)gi * NPOL, vin);
 #pragma unroll
                 for (int p = 0; p < NPOL; p++) {
                     const float2 V = vin[p], y = acc[p];
@@ -110,9 +189,7 @@ __device__ inline void degrid_item(const DegridArgs &a, const WorkItem wk, float
 #pragma unroll
             for (int p = 0; p < NPOL; p++) out[p] = acc[p];
         }
-        float2 *dst = a.vis_out + (int64_t)gi * NPOL;
-#pragma unroll
-        for (int p = 0; p < NPOL; p++) dst[p] = out[p];
+        store_record<NPOL>(a.vis_out + (int64_t)gi * NPOL, out);
     }
     if (want_g && a.ant_in_lds) {
         __syncthreads();
@@ -123,6 +200,5 @@ __device__ inline void degrid_item(const DegridArgs &a, const WorkItem wk, float
         }
     }
 }
-
 
 } // namespace mwg

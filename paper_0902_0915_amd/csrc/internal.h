@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -80,6 +81,12 @@ class TmpScope {
   private:
     TmpPool *own = nullptr;  // null when an enclosing scope is already active on this thread
 };
+
+// Runs job(i, stream) for every i in [0, n) on up to 8 host threads, each issuing to a stream
+// of its own that first waits for the work already on `after`, each with its own pool of
+// temporaries (workers.cpp). Jobs must touch disjoint state. Returns the first error; all
+// device work of the jobs has finished when it returns.
+Status parallel_instances(int device, int n, hipStream_t after, const std::function<Status(int, hipStream_t)> &job);
 
 // Smallest r with 2^r >= v (the exponent of a power-of-two tile size).
 inline int ilog2(int v) {

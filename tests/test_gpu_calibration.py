@@ -140,6 +140,30 @@ def test_peel_edges(mw, small):
         assert e.value.status == mw.MW_ERR_STATE
 
 
+def test_misaligned_visibility_arrays_are_refused(mw, small):
+    """With two polarisations a visibility record is read and written as one 16-byte access:
+    arrays at an 8-byte offset are refused (MW_ERR_INVALID_ARG) by the solve, peel and
+    degrid calls, and the aligned calls on the same data succeed."""
+    import torch
+    ng = small.ngroups
+    flat = torch.zeros(2 * ng + 1, dtype=torch.complex64, device="cuda")
+    odd = flat[1:].view(ng, 2)
+    assert odd.data_ptr() % 16 == 8
+    even = torch.ones((ng, 2), dtype=torch.complex64, device="cuda")
+    with _plan(mw, small, npol=2) as plan:
+        for call in (lambda: plan.solve_gains(odd, even), lambda: plan.solve_gains(even, odd),
+                     lambda: plan.peel(odd, np.array([[0.0, 0.0, 1.0]])),
+                     lambda: plan.degrid(torch.zeros((2, small.ny, small.nx), dtype=torch.complex64,
+                                                     device="cuda"), out=odd)):
+            with pytest.raises(mw.MwError) as e:
+                call()
+            assert e.value.status == mw.MW_ERR_INVALID_ARG
+        plan.solve_gains(even, even)
+        plan.peel(even, np.array([[0.0, 0.0, 1.0]]))
+        plan.degrid(torch.zeros((2, small.ny, small.nx), dtype=torch.complex64, device="cuda"))
+        torch.cuda.synchronize()
+
+
 def test_peel_mwa_scale_removes_a_calibrator_and_finds_its_gains():
     """The MWA-scale workload (512 antennas, 133,955,584 visibilities, 4 polarisations) as
     observed through known antenna gains: one bright calibrator plus the 1000-source sky.
