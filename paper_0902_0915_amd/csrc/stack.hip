@@ -101,18 +101,104 @@ struct StackArgs {
     const WorkItem *work;
     float2 *grid;
     int nx, ny, T, ntx, O, nchan, accumulate;
-    // per clipped footprint width n (1 ... 64): the rows one round of 64 lanes covers
-    // (64 / n) and the multiplier m = ceil(2^16 / n) with lane / n = (lane * m) >> 16 for
-    // every lane < 64, so that a candidate needs no integer division
-    int rounds_rows[65], div_mul[65];
 };
 
 __device__ inline float rl_f(float x, int j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
 
-// Row rounds of a candidate's clipped footprint whose tap loads are issued together.
-constexpr int kStackRounds = 8;
+// Row rounds of a candidate's clipped footprint whose tap loads are issued together (4 was
+// measured faster than 2, 8, 16 or 24 on the beam x w-plane workload).
+constexpr int kStackRounds = 4;
+
+// A candidate of the stack gridder, set up and with the tap loads of its first chunk issued.
+template <int NPOL>
+struct Cand {
+    int ya, yb, rpi, rl, o0, rowoff, S;  // rows [ya, yb]; tap row of grid row y: y + rowoff
+    bool on;                             // this lane covers a footprint column
+    const float2 *kb;                    // this lane's tap column
+    float2 v[NPOL];                      // the candidate's weighted visibilities
+    float2 K[kStackRounds];              // taps of the first chunk
+};
+
+// Row-round chunk at y0 of candidate c with taps K: the LDS read-add-writes.
+template <int NPOL>
+__device__ inline void stack_rmw(const Cand<NPOL> &c, int y0, const float2 (&K)[kStackRounds], float2 *tile, int T,
+                                 int ty0) {
+#pragma unroll
+    for (int it = 0; it < kStackRounds; it++) {
+        const int yy = y0 + it * c.rpi + c.rl;
+        if (c.on && yy <= c.yb) {
+            const int o = (yy - ty0) * T + c.o0;
+#pragma unroll
+            for (int q = 0; q < NPOL; q++) {
+                float2 acc = tile[q * T * T + o];
+                acc.x += K[it].x * c.v[q].x - K[it].y * c.v[q].y;
+                acc.y += K[it].x * c.v[q].y + K[it].y * c.v[q].x;
+                tile[q * T * T + o] = acc;
+            }
+        }
+    }
+}
+
+// Tap loads of the chunk at y0, issued by every lane without a branch (a branch around each
+// load would make the compiler wait for all loads in flight before the first use): a lane
+// outside the footprint reads the tap of the footprint's last row in its column, an address
+// in a line the active lanes fetch anyway, and keeps zero.
+template <int NPOL>
+__device__ inline void stack_load(const Cand<NPOL> &c, int y0, float2 (&K)[kStackRounds]) {
+#pragma unroll
+    for (int it = 0; it < kStackRounds; it++) {
+        const int yy = y0 + it * c.rpi + c.rl;
+        const float2 k = c.kb[(int64_t)(min(yy, c.yb) + c.rowoff) * c.S];
+        K[it] = (c.on && yy <= c.yb) ? k : make_float2(0.f, 0.f);
+    }
+}
+
+// Takes the next staged candidate of `todo` (its footprint meets the band), sets it up and
+// issues its first chunk's tap loads; with `todo` empty, a dummy whose lanes are all off.
+template <int NPOL>
+__device__ inline void stack_prep(const StackArgs &a, uint64_t &todo, uint32_t qp, int qS, int64_t qoff,
+                                  const float2 (&qv)[NPOL], int lane, int tab_rows, int tab_mul, int tx0, int ylo,
+                                  int yhi, int T, Cand<NPOL> &c) {
+    const bool real = todo != 0;
+    const int j = real ? (int)__builtin_ctzll(todo) : 0;
+    todo = real ? todo & (todo - 1) : 0;
+    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)qp, j);
+    const int S = __builtin_amdgcn_readlane(qS, j);
+    const uint32_t olo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)qoff, j);
+    const uint32_t ohi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)qoff >> 32), j);
+    const int64_t koff = (int64_t)(((uint64_t)ohi << 32) | olo);
+    const int h = (S - 1) / 2;
+    const int cx = (int)(p & 0xFFFu), cy = (int)((p >> 12) & 0xFFFu);
+    const int px = (int)((p >> 24) & 0xFu), py = (int)(p >> 28);
+    c.ya = max(cy - h, ylo);
+    c.yb = real ? min(cy + h, yhi) : c.ya - 1;
+    const int xa = max(cx - h, tx0), xb = real ? min(cx + h, tx0 + T - 1) : xa;
+#pragma unroll
+    for (int q = 0; q < NPOL; q++) c.v[q] = make_float2(rl_f(qv[q].x, j), rl_f(qv[q].y, j));
+    const int ncol = xb - xa + 1;
+    c.rpi = __builtin_amdgcn_readlane(tab_rows, ncol - 1);
+    c.rl = (lane * __builtin_amdgcn_readlane(tab_mul, ncol - 1)) >> 16;
+    const int cl = lane - c.rl * ncol;
+    c.on = real && c.rl < c.rpi;
+    c.S = S;
+    c.rowoff = h - cy;
+    c.kb = a.kstack + koff + ((int64_t)(py * a.O + px) * S) * S + (cl + xa - cx + h);
+    c.o0 = xa + cl - tx0;
+    stack_load<NPOL>(c, c.ya, c.K);
+}
+
+// The LDS work of a prepared candidate: its first chunk, then the others chunk by chunk.
+template <int NPOL>
+__device__ inline void stack_finish(const Cand<NPOL> &c, float2 *tile, int T, int ty0) {
+    stack_rmw<NPOL>(c, c.ya, c.K, tile, T, ty0);
+    for (int y0 = c.ya + kStackRounds * c.rpi; y0 <= c.yb; y0 += kStackRounds * c.rpi) {
+        float2 K[kStackRounds];
+        stack_load<NPOL>(c, y0, K);
+        stack_rmw<NPOL>(c, y0, K, tile, T, ty0);
+    }
+}
 
 // One wavefront per work item (tile, candidate range, row band); private LDS tile.
 template <int NPOL>
@@ -125,6 +211,11 @@ __global__ __launch_bounds__(512) void k_grid_stack(StackArgs a, int nwork) {
     if (widx >= nwork) return;
     const int T = a.T;
     float2 *tile = (float2 *)smem + (size_t)wave * NPOL * T * T;
+    // Per clipped footprint width n = lane + 1 (1 ... 64; tiles are at most 64 wide): the rows
+    // one round of 64 lanes covers (64 / n) and the multiplier m = ceil(2^16 / n) with
+    // j / n = (j * m) >> 16 for every j < 64. A candidate picks its width's entries with
+    // v_readlane, so that it needs neither an integer division nor a memory load.
+    const int tab_rows = 64 / (lane + 1), tab_mul = (65536 + lane) / (lane + 1);
     const WorkItem wk = a.work[widx];
     const int r0 = wk.pad & 0xFFFF, r1 = wk.pad >> 16;
     const int tx0 = (wk.tile % a.ntx) * T, ty0 = (wk.tile / a.ntx) * T;
@@ -162,52 +253,24 @@ __global__ __launch_bounds__(512) void k_grid_stack(StackArgs a, int nwork) {
                 qv[p] = make_float2(mr * v.x - mi * v.y, mr * v.y + mi * v.x);
             }
         }
-        for (int j = 0; j < cnt; j++) {
-            const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)qp, j);
-            const int S = __builtin_amdgcn_readlane(qS, j);
-            const uint32_t olo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)qoff, j);
-            const uint32_t ohi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)qoff >> 32), j);
-            const int64_t koff = (int64_t)(((uint64_t)ohi << 32) | olo);
-            const int h = (S - 1) / 2;
-            const int cx = (int)(p & 0xFFFu), cy = (int)((p >> 12) & 0xFFFu);
-            const int px = (int)((p >> 24) & 0xFu), py = (int)(p >> 28);
-            const int ya = max(cy - h, ylo), yb = min(cy + h, yhi);
-            const int xa = max(cx - h, tx0), xb = min(cx + h, tx0 + T - 1);
-            if (ya > yb || xa > xb) continue;
-            float2 v[NPOL];
-#pragma unroll
-            for (int q = 0; q < NPOL; q++) v[q] = make_float2(rl_f(qv[q].x, j), rl_f(qv[q].y, j));
-            const int ncol = xb - xa + 1;
-            const int rpi = a.rounds_rows[ncol];
-            const int rl = (lane * a.div_mul[ncol]) >> 16, cl = lane - rl * ncol;
-            const bool on = rl < rpi;
-            const float2 *kb = a.kstack + koff + ((int64_t)(py * a.O + px) * S) * S + (cl + xa - cx + h);
-            const int o0 = (xa + cl - tx0);
-            // the clipped footprint in chunks of kStackRounds row rounds: every tap load of a
-            // chunk is issued before any of its LDS read-modify-writes, so a candidate waits
-            // for the cache about once per chunk instead of once per row round
-            for (int y0 = ya; y0 <= yb; y0 += kStackRounds * rpi) {
-                float2 K[kStackRounds];
-#pragma unroll
-                for (int it = 0; it < kStackRounds; it++) {
-                    const int yy = y0 + it * rpi + rl;
-                    K[it] = (on && yy <= yb) ? kb[(int64_t)(yy - cy + h) * S] : make_float2(0.f, 0.f);
-                }
-#pragma unroll
-                for (int it = 0; it < kStackRounds; it++) {
-                    const int yy = y0 + it * rpi + rl;
-                    if (on && yy <= yb) {
-                        const int o = (yy - ty0) * T + o0;
-#pragma unroll
-                        for (int q = 0; q < NPOL; q++) {
-                            float2 acc = tile[q * T * T + o];
-                            acc.x += K[it].x * v[q].x - K[it].y * v[q].y;
-                            acc.y += K[it].x * v[q].y + K[it].y * v[q].x;
-                            tile[q * T * T + o] = acc;
-                        }
-                    }
-                }
-            }
+        // candidates whose clipped footprint meets this item's band of rows
+        uint64_t todo;
+        {
+            const int hS = (qS - 1) / 2;
+            const int cxl = (int)(qp & 0xFFFu), cyl = (int)((qp >> 12) & 0xFFFu);
+            const bool meets = lane < cnt && max(cyl - hS, ylo) <= min(cyl + hS, yhi) &&
+                               max(cxl - hS, tx0) <= min(cxl + hS, tx0 + T - 1);
+            todo = __ballot(meets);
+        }
+        // Candidates in pairs: both are set up and both first chunks' tap loads issued, in
+        // straight-line code (a missing second candidate is a dummy whose lanes are all off),
+        // before the LDS work of either, so that the two load latencies overlap.
+        while (todo) {
+            Cand<NPOL> A, B;
+            stack_prep<NPOL>(a, todo, qp, qS, qoff, qv, lane, tab_rows, tab_mul, tx0, ylo, yhi, T, A);
+            stack_prep<NPOL>(a, todo, qp, qS, qoff, qv, lane, tab_rows, tab_mul, tx0, ylo, yhi, T, B);
+            stack_finish<NPOL>(A, tile, T, ty0);
+            stack_finish<NPOL>(B, tile, T, ty0);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -459,10 +522,6 @@ Status launch_grid_stack(Instance &I, const float2 *vis, const float2 *gains, fl
     a.O = I.O;
     a.nchan = I.nchan;
     a.accumulate = 1; // the grid was zeroed above in overwrite mode
-    for (int n = 1; n <= 64; n++) {
-        a.rounds_rows[n] = 64 / n;
-        a.div_mul[n] = (65536 + n - 1) / n;
-    }
     switch (I.npol) {
     case 1: return grid_stack_npol<1>(I, a, s);
     case 2: return grid_stack_npol<2>(I, a, s);
