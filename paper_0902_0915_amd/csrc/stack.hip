@@ -200,7 +200,8 @@ __device__ inline void stack_finish(const Cand<NPOL> &c, float2 *tile, int T, in
     }
 }
 
-// One wavefront per work item (tile, candidate range, row band); private LDS tile.
+// One wavefront per work item (tile, candidate range, row band); private LDS tile. At most 8
+// waves per workgroup (the plan refuses more).
 template <int NPOL>
 __global__ __launch_bounds__(512) void k_grid_stack(StackArgs a, int nwork) {
     extern __shared__ __align__(16) float smem[];

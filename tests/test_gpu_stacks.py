@@ -38,7 +38,8 @@ def _kw(wl, gains=None):
 
 
 @pytest.mark.parametrize("npol", [1, 2])
-@pytest.mark.parametrize("tuning", [None, dict(tile=16), dict(tile=8, split=64)], ids=str)
+@pytest.mark.parametrize("tuning", [None, dict(tile=32), dict(tile=8, split=64), dict(tile=16, wg_waves=4)],
+                         ids=str)
 def test_stack_grid_parity(mw, npol, tuning):
     wl = _stack_wl(npol)
     rng = np.random.default_rng(npol)
@@ -93,3 +94,12 @@ def test_stack_image_correction_refused(mw):
             plan.image(z, correct=True)
         assert e.value.status == mw.MW_ERR_STATE
         plan.image(z, correct=False)  # the plain transform is allowed
+
+
+def test_stack_workgroup_limit(mw):
+    """The stack gridder's workgroups hold at most 8 waves (its launch bound): a plan asking
+    for 16 is refused when it is built, with MW_ERR_UNSUPPORTED, not at its first launch."""
+    wl = _stack_wl(1)
+    with pytest.raises(mw.MwError) as e:
+        mw.Plan(mw.InstanceSpec.from_workload(wl), tuning=dict(wg_waves=16))
+    assert e.value.status == mw.MW_ERR_UNSUPPORTED
