@@ -107,17 +107,19 @@ typedef struct {
 typedef struct {
     int32_t tile;       /* uv tile edge in cells: 8, 16, 32 or 64 (8 needs W <= 15) */
     int32_t split;      /* max groups per work item (heavy tiles are split), >= 64 */
-    int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 (1 and 2 with variant 4) */
+    int32_t wg_waves;   /* wavefronts per workgroup: 4, 8 or 16 (1 and 2 with variants 4 and 6) */
     int32_t order;      /* 1 = groups sorted by cell (then row sub-position) within a tile,
                            cells row by row, 2 = input order, 3 (default) = as 1 with the
                            cells ranked line by line across the direction from the grid
                            centre to the tile (rows or columns for tiles above 16) */
     int32_t variant;    /* gridder: 1 = tap lanes, 2 = column lanes, 3 = scatter,
                            4 = column lanes with a private tile per wavefront,
-                           5 = kernel stacks, gathered by output tile (chosen for stacks) */
+                           5 = kernel stacks, gathered by output tile (chosen for stacks),
+                           6 = as 4 over a work list whose (cell, py) runs are padded to
+                           blocks of 4 (flush 1 or 2, schedule 1, 3 <= W <= 7) */
     int32_t flush;      /* 1 = atomic adds of each finished tile into the zeroed grid,
                            2 = tiles to a scratch buffer, then a merge pass writes the grid
-                           (with variant 4 the result is then bit-reproducible),
+                           (with variants 4 and 6 the result is then bit-reproducible),
                            3 = owner tiles (variant 4, schedule 1, tile >= W - 1): each
                            output tile is gridded by one wavefront from every group whose
                            footprint reaches it and written once, no scratch, no merge
@@ -174,7 +176,7 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst,
  * vis[i]: device complex64 [ngroups][npol]. gains: NULL, or gains[i] NULL or device
  * complex64 [nant]. grid[i]: device complex64 [npol][ny][nx]. accumulate = 0 overwrites the
  * grid (zeroing is part of the call); 1 adds to it. FP32 accumulation; the summation order
- * is fixed (bit-reproducible results) only with variant 4 and flush 2 or 3.
+ * is fixed (bit-reproducible results) only with variant 4 and flush 2 or 3, and variant 6 with flush 2.
  * Errors: MW_ERR_INVALID_ARG (null plan/arrays), MW_ERR_STATE (gains for an instance planned
  * without antennas), MW_ERR_HIP (launch failure).
  */

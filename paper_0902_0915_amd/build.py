@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmwagrid.so")
 SOURCES = ["abi.cpp", "pswf.cpp", "plan.hip", "grid.hip", "degrid.hip", "image.hip", "fft.hip",
-           "stack.hip", "batched.hip", "tuner.cpp", "stokes.hip", "owner.hip", "calib.hip", "weighting.hip", "wstack.hip", "workers.cpp"]
+           "stack.hip", "batched.hip", "tuner.cpp", "stokes.hip", "owner.hip", "calib.hip", "weighting.hip", "wstack.hip", "workers.cpp", "runs.hip"]
 ARCH = os.environ.get("MWG_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-x", "hip", "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -94,7 +94,7 @@ mwg::Status validate_tuning(const mw_tuning &t) {
         t.wg_waves != 16)
         return make_error(MW_ERR_INVALID_ARG, "tuning.wg_waves must be 0, 1, 2, 4, 8 or 16");
     if (t.order < 0 || t.order > 3) return make_error(MW_ERR_INVALID_ARG, "tuning.order must be 0 ... 3");
-    if (t.variant < 0 || t.variant > 5) return make_error(MW_ERR_INVALID_ARG, "tuning.variant must be 0..5");
+    if (t.variant < 0 || t.variant > 6) return make_error(MW_ERR_INVALID_ARG, "tuning.variant must be 0..6");
     if (t.flush < 0 || t.flush > 3) return make_error(MW_ERR_INVALID_ARG, "tuning.flush must be 0 ... 3");
     if (t.schedule < 0 || t.schedule > 3) return make_error(MW_ERR_INVALID_ARG, "tuning.schedule must be 0 ... 3");
     return mwg::Status::Ok();

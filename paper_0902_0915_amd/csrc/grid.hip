@@ -30,6 +30,7 @@ size_t taplanes_lds(int npol, int T, int W, int O, int waves);
 size_t collanes_lds(int npol, int T, int W, int O, int waves);
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
 size_t owner_lds(int npol, int T, int W, int O, int waves);
+size_t blocktiles_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
 Status ensure_partial(Instance &I, hipStream_t s);
 
@@ -430,6 +431,50 @@ __global__ __launch_bounds__(1024) void k_grid_wavetiles(GridArgs a, int flush, 
     wavetile_item<NPOL, W>(c, lane);
 }
 
+// Variant 6: the wave-tile gridder over the plan's block-padded work list (schedule 1).
+template <int NPOL, int W>
+__global__ __launch_bounds__(1024) void k_grid_blocktiles(GridArgs a, int flush, int nwork) {
+    constexpr int NC = 2 * NPOL;
+    extern __shared__ __align__(16) float smem[];
+    const int nthreads = blockDim.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = nthreads >> 6;
+    const int ntab = a.O * 8;
+    float *ltab = smem;
+    for (int i = tid; i < ntab; i += nthreads) ltab[i] = a.tab8[i];
+    __syncthreads();
+    const int widx = blockIdx.x * nwaves + wave;
+    if (widx >= nwork) return;
+    const int R = a.T + W - 1;
+    ItemCtx c;
+    c.sv = smem + ntab + wave * blocktile_per_wave(NC, a.plane);
+    c.tile = c.sv + blocktile_stage_floats(NC);
+    for (int i = lane; i < NC * a.plane; i += 64) c.tile[i] = 0.0f;
+    const WorkItem wk = a.work[widx];
+    c.vis = a.vis;
+    c.gains = a.gains;
+    c.perm = a.perm;
+    c.scode = a.scode;
+    c.sant = a.sant;
+    c.sw = a.sw;
+    c.tapk = a.tapk;
+    c.ltab = ltab;
+    c.grid = a.grid;
+    c.partial = flush == 2 ? a.partial + (int64_t)widx * NC * R * R : nullptr;
+    c.accumulate = a.accumulate;
+    c.wb = wk.begin;
+    c.we = wk.end;
+    c.tx0 = (wk.tile % a.ntx) * a.T;
+    c.ty0 = (wk.tile / a.ntx) * a.T;
+    c.T = a.T;
+    c.STR = a.str;
+    c.PL = a.plane;
+    c.nx = a.nx;
+    c.ny = a.ny;
+    c.flush = flush;
+    blocktile_item<NPOL, W>(c, lane);
+}
+
 // Schedule 3 of variant 4: the waves of a workgroup share its items. Slot j of the
 // workgroup (wave j) grids part k of the nsub equal parts of item coop[j].x into its private
 // tile; after a barrier the workgroup sums each item's nsub tiles in wave order into the
@@ -582,8 +627,9 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s,
                         size_t partial_cap = 0) {
     const Launch &L = I.L;
     const int R = L.tile + I.W - 1;
-    a.str = L.variant == 4 ? R : tile_stride(R, I.W);
-    a.plane = (L.variant == 2 || L.variant == 4) ? tile_plane2(R, a.str, I.W) : tile_plane(R, a.str);
+    a.str = (L.variant == 4 || L.variant == 6) ? R : tile_stride(R, I.W);
+    a.plane = (L.variant == 2 || L.variant == 4 || L.variant == 6) ? tile_plane2(R, a.str, I.W)
+                                                                    : tile_plane(R, a.str);
     const int flush = L.flush;
     if (partial_in) {
         const size_t need = sizeof(float) * (size_t)std::max(I.nwork, 1) * 2 * I.npol * R * R;
@@ -654,6 +700,24 @@ Status launch_grid_npol(Instance &I, GridArgs &a, int accumulate, hipStream_t s,
                 default: return make_error(MW_ERR_UNSUPPORTED, "variant 4 needs W in {3, 5, 7}");
                 }
             }
+        } else if (L.variant == 6) {
+            // the block-padded list replaces the sorted arrays (same items, same partial slices)
+            if (!I.bwork || I.block_tile != L.tile)
+                return make_error(MW_ERR_STATE, "variant 6 needs the plan's block-padded schedule");
+            a.work = I.bwork;
+            a.perm = I.bperm;
+            a.scode = I.bcode;
+            a.sw = I.bsw;
+            a.sant = I.bsant;
+            const size_t lds = blocktiles_lds(NPOL, L.tile, I.W, I.O, L.wg_waves);
+            if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
+            const dim3 g((nwork + L.wg_waves - 1) / L.wg_waves), b(64 * L.wg_waves);
+            switch (I.W) {
+            case 3: hipLaunchKernelGGL((k_grid_blocktiles<NPOL, 3>), g, b, lds, s, a, flush, nwork); break;
+            case 5: hipLaunchKernelGGL((k_grid_blocktiles<NPOL, 5>), g, b, lds, s, a, flush, nwork); break;
+            case 7: hipLaunchKernelGGL((k_grid_blocktiles<NPOL, 7>), g, b, lds, s, a, flush, nwork); break;
+            default: return make_error(MW_ERR_UNSUPPORTED, "variant 6 needs W in {3, 5, 7}");
+            }
         } else {
             const size_t lds = scatter_lds(NPOL, L.tile, I.W, I.O);
             if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "tile needs %zu B of LDS", lds);
@@ -696,6 +760,11 @@ size_t collanes_lds(int npol, int T, int W, int O, int waves) {
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves) {
     const int R = T + W - 1, PL = tile_plane2(R, R, W);
     return 4 * ((size_t)O * 8 + (size_t)waves * wavetile_per_wave(2 * npol, PL));
+}
+
+size_t blocktiles_lds(int npol, int T, int W, int O, int waves) {
+    const int R = T + W - 1, PL = tile_plane2(R, R, W);
+    return 4 * ((size_t)O * 8 + (size_t)waves * blocktile_per_wave(2 * npol, PL));
 }
 
 size_t owner_lds(int npol, int T, int W, int O, int waves) {

@@ -120,6 +120,63 @@ constexpr int kStageFloats = kStageGroups * kStageStride;
 // of PL floats), rounded so that every wave's staging area stays 16-byte aligned.
 __host__ __device__ inline int wavetile_per_wave(int nc, int pl) { return kStageFloats + ((nc * pl + 3) & ~3); }
 
+// Writes a wave's finished private tile out (flush 1: atomic adds into the grid, 2: the
+// item's partial slice, cell-major; 3: the owner tile's T x T cells, once).
+template <int NPOL, int W>
+__device__ inline void wavetile_flush(const ItemCtx &c, int lane) {
+    constexpr int NC = 2 * NPOL;
+    const int h = (W - 1) / 2, R = c.T + W - 1, STR = c.STR, PL = c.PL;
+    const int tx0 = c.tx0, ty0 = c.ty0;
+    float *tile = c.tile;
+    (void)STR;
+    if (c.flush == 1) {
+        for (int idx = lane; idx < R * R; idx += 64) {
+            const int r = idx / R, col = idx - r * R;
+            const int gy = ty0 - h + r, gx = tx0 - h + col;
+            if (gy < 0 || gy >= c.ny || gx < 0 || gx >= c.nx) continue;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                const float re = tile[(2 * p) * PL + r * STR + col];
+                const float im = tile[(2 * p + 1) * PL + r * STR + col];
+                float *dst = (float *)(c.grid + ((int64_t)p * c.ny + gy) * c.nx + gx);
+                if (re != 0.0f) atomicAdd(dst, re);
+                if (im != 0.0f) atomicAdd(dst + 1, im);
+            }
+        }
+    } else if (c.flush == 3) {
+        // the output tile's T x T cells at LDS offset (2h, 2h), each written once
+        const int T = c.T, m = 2 * h;
+        for (int idx = lane; idx < T * T; idx += 64) {
+            const int r = idx / T, col = idx - r * T;
+            const int gy = ty0 + r, gx = tx0 + col;
+            if (gy >= c.ny || gx >= c.nx) continue;
+            const int o = (r + m) * STR + col + m;
+#pragma unroll
+            for (int p = 0; p < NPOL; p++) {
+                float2 v = make_float2(tile[(2 * p) * PL + o], tile[(2 * p + 1) * PL + o]);
+                float2 *dst = c.grid + ((int64_t)p * c.ny + gy) * c.nx + gx;
+                if (c.accumulate) {
+                    const float2 old = *dst;
+                    v.x += old.x;
+                    v.y += old.y;
+                }
+                *dst = v;
+            }
+        }
+    } else if (c.flush == 2) {
+        // the item's slice of the partial buffer: cell-major, the NC components of a cell
+        // contiguous
+        float *out = c.partial;
+        for (int idx = lane; idx < R * R; idx += 64) {
+            const int r = idx / R, col = idx - r * R;
+            float v[NC];
+#pragma unroll
+            for (int q = 0; q < NC; q++) v[q] = tile[q * PL + r * STR + col];
+            store_cell<NC>(out + (int64_t)idx * NC, v);
+        }
+    }
+}
+
 // Grids work item c with this wavefront (lanes as in variant 2) into its private tile and
 // writes the tile out (flush 1: atomic adds into the grid, 2: the item's partial slice; 0:
 // the tile stays in LDS for the caller). The tile must be zero on entry.
@@ -268,53 +325,159 @@ __device__ inline void wavetile_item(const ItemCtx &c, int lane) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // this wave's tile to HBM
-    if (c.flush == 1) {
-        for (int idx = lane; idx < R * R; idx += 64) {
-            const int r = idx / R, col = idx - r * R;
-            const int gy = ty0 - h + r, gx = tx0 - h + col;
-            if (gy < 0 || gy >= c.ny || gx < 0 || gx >= c.nx) continue;
+    wavetile_flush<NPOL, W>(c, lane);
+}
+
+// Variant 6 ("block runs"): the work list of variant 4 with every (cell, py) run of a work
+// item padded, in the plan, to a multiple of kRunBlock entries (dummies have group index
+// kDummyGroup and their run's code, and are staged as zero visibilities). Every block of
+// kRunBlock consecutive entries then belongs to one run: a block costs one run-start test,
+// one 16-byte LDS read of its visibility components and one of its column taps per lane, and
+// kRunBlock FMAs, with no per-group branch. The staging area is component-major: a row of
+// kBlockStageStride floats per visibility component and per column tap, 32 entries wide.
+// On the MWA-scale workload (runs of 4.9 groups on average, a quarter of them single) the
+// padding adds 38 % entries and the launch takes 0.72 ms against variant 4's 0.67 ms, so it
+// is not the default.
+constexpr int kRunBlock = 4;
+constexpr uint32_t kDummyGroup = 0xFFFFFFFFu;
+constexpr int kBlockStageStride = 36;  // rows 36 floats apart: 8 rows' 16-byte reads hit distinct banks
+__host__ __device__ inline int blocktile_stage_floats(int nc) { return (nc + 8) * kBlockStageStride; }
+__host__ __device__ inline int blocktile_per_wave(int nc, int pl) {
+    return blocktile_stage_floats(nc) + ((nc * pl + 3) & ~3);
+}
+
+template <int NPOL, int W>
+__device__ inline void blocktile_item(const ItemCtx &c, int lane) {
+    constexpr int NC = 2 * NPOL;
+    constexpr int NSG = 8 / NC;
+    constexpr int NR = (W + NSG - 1) / NSG;
+    constexpr int SS = kBlockStageStride;
+    const int STR = c.STR, PL = c.PL;
+    float *tile = c.tile, *sv = c.sv;
+    const float *ltab = c.ltab;
+    const int wb = c.wb, we = c.we;
+    const int t = lane % W;
+    const int cc = (lane / W) % NC;
+    const int sg = lane / (W * NC);
+    const bool active = lane < W * NC * NSG;
+    const int loff = active ? cc * PL + sg * STR + t : 0;
+    const float *vrow = sv + cc * SS;          // component cc of the staged entries
+    const float *trow = sv + (NC + t) * SS;    // column tap T[px][t] of the staged entries
+    float acc[NR], ty[NR];
 #pragma unroll
-            for (int p = 0; p < NPOL; p++) {
-                const float re = tile[(2 * p) * PL + r * STR + col];
-                const float im = tile[(2 * p + 1) * PL + r * STR + col];
-                float *dst = (float *)(c.grid + ((int64_t)p * c.ny + gy) * c.nx + gx);
-                if (re != 0.0f) atomicAdd(dst, re);
-                if (im != 0.0f) atomicAdd(dst + 1, im);
+    for (int k = 0; k < NR; k++) {
+        acc[k] = 0.0f;
+        ty[k] = 0.0f;
+    }
+    float asum = 0.0f;
+    int cur = -1, curkey = -1;
+    auto start_run = [&](uint32_t qj, bool newcell) {
+#pragma unroll
+        for (int k = 0; k < NR; k++) acc[k] = fmaf(ty[k], asum, acc[k]);
+        asum = 0.0f;
+        if (newcell) {
+            if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
+#pragma unroll
+            for (int k = 0; k < NR; k++) acc[k] = 0.0f;
+            cur = (int)(qj & 0xFFFFu);
+        }
+        curkey = (int)(qj & 0xFF00FFFFu);
+        const int ty8 = (int)(qj >> 24);
+        if constexpr (NSG == 1) {
+#pragma unroll
+            for (int k = 0; k < NR; k++) ty[k] = c.tapk[ty8 + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NR; k++) {
+                const int sr = sg + NSG * k;
+                ty[k] = ltab[ty8 + (sr < W ? sr : 0)];
             }
         }
-    } else if (c.flush == 3) {
-        // the output tile's T x T cells at LDS offset (2h, 2h), each written once
-        const int T = c.T, m = 2 * h;
-        for (int idx = lane; idx < T * T; idx += 64) {
-            const int r = idx / T, col = idx - r * T;
-            const int gy = ty0 + r, gx = tx0 + col;
-            if (gy >= c.ny || gx >= c.nx) continue;
-            const int o = (r + m) * STR + col + m;
+    };
+    // lane j holds entry j of the batch: its code and visibilities (zero for a dummy); the
+    // next batch's are in flight while one is accumulated, the permutation two batches ahead
+    uint32_t gA = (wb + lane < we) ? c.perm[wb + lane] : kDummyGroup;
+    uint32_t gB = (wb + 64 + lane < we) ? c.perm[wb + 64 + lane] : kDummyGroup;
+    uint32_t qn = (wb + lane < we) ? c.scode[wb + lane] : 0u;
+    float2 vn[NPOL];
 #pragma unroll
-            for (int p = 0; p < NPOL; p++) {
-                float2 v = make_float2(tile[(2 * p) * PL + o], tile[(2 * p + 1) * PL + o]);
-                float2 *dst = c.grid + ((int64_t)p * c.ny + gy) * c.nx + gx;
-                if (c.accumulate) {
-                    const float2 old = *dst;
-                    v.x += old.x;
-                    v.y += old.y;
+    for (int p = 0; p < NPOL; p++) vn[p] = make_float2(0.f, 0.f);
+    if (gA != kDummyGroup) core_fetch<NPOL>(c, wb + lane, gA, vn);
+    for (int base = wb; base < we; base += 64) {
+        const int cnt = (we - base) < 64 ? (we - base) : 64;  // a multiple of kRunBlock
+        const uint32_t qcur = qn;
+        float2 vc[NPOL];
+#pragma unroll
+        for (int p = 0; p < NPOL; p++) {
+            vc[p] = vn[p];
+            vn[p] = make_float2(0.f, 0.f);
+        }
+        if (base + 64 + lane < we) {
+            if (gB != kDummyGroup) core_fetch<NPOL>(c, base + 64 + lane, gB, vn);
+            qn = c.scode[base + 64 + lane];
+        }
+        gB = (base + 128 + lane < we) ? c.perm[base + 128 + lane] : kDummyGroup;
+        const int cellj = (int)(qcur & 0xFFFFu);
+        const int keyj = (int)(qcur & 0xFF00FFFFu);
+        int prevc = __shfl_up(cellj, 1, 64);
+        int prevk = __shfl_up(keyj, 1, 64);
+        if (lane == 0) {
+            prevc = cur;
+            prevk = curkey;
+        }
+        // run and cell starts fall on block boundaries only
+        const uint64_t kstarts = __ballot(lane < cnt && keyj != prevk);
+        const uint64_t cstarts = __ballot(lane < cnt && cellj != prevc);
+        for (int h0 = 0; h0 < cnt; h0 += 32) {
+            // stage entries [h0, h0 + 32): components and column-tap rows, component-major
+            const int jo = lane - h0;
+            if (jo >= 0 && jo < 32) {
+                const bool live = lane < cnt;
+#pragma unroll
+                for (int p = 0; p < NPOL; p++) {
+                    sv[(2 * p) * SS + jo] = live ? vc[p].x : 0.0f;
+                    sv[(2 * p + 1) * SS + jo] = live ? vc[p].y : 0.0f;
                 }
-                *dst = v;
+                const float4 *row = (const float4 *)(ltab + (live ? ((qcur >> 16) & 0xFFu) : 0u));
+                const float4 r0 = row[0], r1 = row[1];
+                float *tr = sv + NC * SS + jo;
+                tr[0 * SS] = r0.x;
+                tr[1 * SS] = r0.y;
+                tr[2 * SS] = r0.z;
+                tr[3 * SS] = r0.w;
+                tr[4 * SS] = r1.x;
+                tr[5 * SS] = r1.y;
+                tr[6 * SS] = r1.z;
+                tr[7 * SS] = r1.w;
             }
-        }
-    } else if (c.flush == 2) {
-        // the item's slice of the partial buffer: cell-major, the NC components of a cell
-        // contiguous
-        float *out = c.partial;
-        for (int idx = lane; idx < R * R; idx += 64) {
-            const int r = idx / R, col = idx - r * R;
-            float v[NC];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int hcnt = (cnt - h0) < 32 ? (cnt - h0) : 32;  // a multiple of kRunBlock
+            const uint64_t ksh = kstarts >> h0, csh = cstarts >> h0;
 #pragma unroll
-            for (int q = 0; q < NC; q++) v[q] = tile[q * PL + r * STR + col];
-            store_cell<NC>(out + (int64_t)idx * NC, v);
+            for (int jb = 0; jb < 32; jb += kRunBlock) {
+                if (jb >= hcnt) break;
+                const float4 v4 = *(const float4 *)(vrow + jb);
+                const float4 t4 = *(const float4 *)(trow + jb);
+                if ((ksh >> jb) & 1u)
+                    start_run((uint32_t)__builtin_amdgcn_readlane((int)qcur, h0 + jb), (csh >> jb) & 1u);
+                asum = fmaf(t4.x, v4.x, asum);
+                asum = fmaf(t4.y, v4.y, asum);
+                asum = fmaf(t4.z, v4.z, asum);
+                asum = fmaf(t4.w, v4.w, asum);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
+    start_run(0u, false);  // close the last run
+    if (cur >= 0 && active) wave_tile_add<NR, NSG, W>(tile + cur + loff, STR, sg, acc);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wavetile_flush<NPOL, W>(c, lane);
 }
 
 // The merge pass over blocks of kMergeB x kMergeB cells, one cell per thread. Every cell is

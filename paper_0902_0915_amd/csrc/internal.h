@@ -205,6 +205,16 @@ struct Instance {
     // prediction and calibration (calib.hip)
     double *uvw_d = nullptr;      // [nrow][3] metres
     double *kf_d = nullptr;       // [nchan] f / c, turns per metre
+    // variant 6: the sorted arrays with every (cell, py) run of a work item padded to a
+    // multiple of 4 entries (runs.hip); same work items, padded ranges
+    int block_tile = 0;           // tile the padded schedule was built for (0: none)
+    int64_t nblocked = 0, cap_blocked = 0;  // padded entries and their capacity
+    size_t cap_bwork = 0;         // capacity of bwork
+    WorkItem *bwork = nullptr;    // [nwork]
+    uint32_t *bperm = nullptr;    // [nblocked + 64] group, or 0xFFFFFFFF for a padding entry
+    uint32_t *bcode = nullptr;    // [nblocked + 64] codes as scode (a padding entry: its run's)
+    float *bsw = nullptr;         // [nblocked] weights (or null)
+    uint32_t *bsant = nullptr;    // [nblocked] antenna pairs (or null)
     int64_t cal_npair = 0;        // antenna pairs (baselines) among the rows
     uint32_t *cal_pant = nullptr; // [npair] a1 | a2 << 16
     int32_t *cal_pstart = nullptr; // [npair + 1] CSR of each pair's rows
@@ -243,6 +253,8 @@ void prolate_tables(int W, int O, int nx, int ny, std::vector<float> &table,
 Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *t, hipStream_t s, bool schedule = true,
                       bool count_tiles = false);
 Status schedule_instance(Instance &I, const Launch &L, hipStream_t s);
+// runs.hip: the block-padded work list of variant 6 from the current sort and codes
+Status build_block_schedule(Instance &I, hipStream_t s);
 Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s);
 
 // stack.hip

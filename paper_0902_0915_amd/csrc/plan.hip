@@ -869,7 +869,8 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         if (!I.stacks) {
             const int R = L.tile + I.W - 1;
             hipLaunchKernelGGL(k_codes, dim3(grid1d(nk)), dim3(kBlock), 0, s, I.spos, nk, tb,
-                               L.variant == 4 ? R : tile_stride_host(R, I.W), I.W, I.O, I.scode);
+                               (L.variant == 4 || L.variant == 6) ? R : tile_stride_host(R, I.W), I.W, I.O,
+                               I.scode);
             MWG_HIP(hipGetLastError());
         }
     }
@@ -877,6 +878,7 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         bool built = false;
         MWG_TRY(build_owner_schedule(I, 0, &built, s));
     }
+    if (L.variant == 6) MWG_TRY(build_block_schedule(I, s));
     return Status::Ok();
 }
 
@@ -891,6 +893,7 @@ size_t taplanes_lds(int npol, int T, int W, int O, int waves);
 size_t collanes_lds(int npol, int T, int W, int O, int waves);
 size_t wavetiles_lds(int npol, int T, int W, int O, int waves);
 size_t owner_lds(int npol, int T, int W, int O, int waves);
+size_t blocktiles_lds(int npol, int T, int W, int O, int waves);
 size_t scatter_lds(int npol, int T, int W, int O);
 
 static Launch default_launch(const Instance &I) {
@@ -947,8 +950,8 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         return make_error(MW_ERR_UNSUPPORTED, "flush 3 is implemented for variant 4 with schedule 1 only");
     if (L.flush == 3 && L.tile < I.W - 1)
         return make_error(MW_ERR_UNSUPPORTED, "flush 3 needs tiles of at least W - 1 cells");
-    if (L.wg_waves < 4 && (I.stacks || L.variant != 4))
-        return make_error(MW_ERR_UNSUPPORTED, "workgroups of %d waves are implemented for variant 4 only", L.wg_waves);
+    if (L.wg_waves < 4 && (I.stacks || (L.variant != 4 && L.variant != 6)))
+        return make_error(MW_ERR_UNSUPPORTED, "workgroups of %d waves are implemented for variants 4 and 6 only", L.wg_waves);
     if (I.stacks) {
         L.variant = 5;
         if (L.wg_waves > 8)
@@ -961,8 +964,10 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
         if (L.tile < 8) return make_error(MW_ERR_UNSUPPORTED, "stack tiles must be >= 8");
     }
     if (!I.stacks) {
-        if ((L.variant == 2 || L.variant == 4) && (I.W > 7 || I.W < 3))
-            return make_error(MW_ERR_UNSUPPORTED, "variants 2 and 4 need 3 <= W <= 7 (W = %d)", I.W);
+        if ((L.variant == 2 || L.variant == 4 || L.variant == 6) && (I.W > 7 || I.W < 3))
+            return make_error(MW_ERR_UNSUPPORTED, "variants 2, 4 and 6 need 3 <= W <= 7 (W = %d)", I.W);
+        if (L.variant == 6 && (L.flush == 3 || L.schedule != 1))
+            return make_error(MW_ERR_UNSUPPORTED, "variant 6 takes flush 1 or 2 and schedule 1");
         if (L.variant == 1 && I.W * I.W > 64)
             return make_error(MW_ERR_UNSUPPORTED, "variant 1 needs W*W <= 64 (W = %d)", I.W);
         auto lds_of = [&](const Launch &X) {
@@ -970,6 +975,7 @@ Status resolve_launch(const Instance &I, const mw_tuning *t, Launch *out) {
                    : X.variant == 2 ? collanes_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
                    : X.variant == 4 ? (X.flush == 3 ? owner_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
                                                     : wavetiles_lds(I.npol, X.tile, I.W, I.O, X.wg_waves))
+                   : X.variant == 6 ? blocktiles_lds(I.npol, X.tile, I.W, I.O, X.wg_waves)
                                     : scatter_lds(I.npol, X.tile, I.W, I.O);
         };
         // private wave tiles of a large tile size may not fit: without an explicit variant,

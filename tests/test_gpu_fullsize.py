@@ -30,6 +30,10 @@ def full():
         back = plan.degrid(G)
         torch.cuda.synchronize()
         out = dict(info=info, G=to_host(G), img=to_host(img), back=to_host(back))
+    # the block-padded gridder (variant 6) on the same data, for a bitwise comparison
+    with mwagrid.Plan(spec, tuning=dict(variant=6, tile=8, flush=2)) as plan6:
+        out["info6"] = plan6.info(0)
+        out["G6"] = to_host(plan6.grid(wl.vis))
     out["vis"] = wl.vis.cpu().numpy()
     out["wl"] = wl
     pos, keep, counts = orc.positions(wl.uvw, wl.freq, wl.nx, wl.ny, wl.du, wl.dv, wl.W, wl.O)
@@ -54,6 +58,12 @@ def test_full_size_grid_whole_by_region(full):
     assert err["dense"] <= TOL and err["rest"] <= TOL, err
     assert err["zero_nonzero_got"] == 0 and err["zero_nonzero_ref"] == 0, err
     assert nl2(G, ref) <= TOL
+
+
+def test_full_size_block_runs_equal_wave_tiles(full):
+    """Variant 6 at full size: the same grid as the benchmarked launch, bit for bit."""
+    assert full["info6"]["variant"] == 6 and full["info6"]["nwork"] == full["info"]["nwork"]
+    np.testing.assert_array_equal(full["G6"], full["G"])
 
 
 def test_full_size_image_of_the_grid(full):

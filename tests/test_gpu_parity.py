@@ -111,6 +111,9 @@ TUNINGS = [
     dict(variant=4, tile=8, flush=3),
     dict(variant=4, tile=16, flush=3, wg_waves=2),
     dict(variant=4, tile=32, flush=3, wg_waves=1, order=2),
+    dict(variant=6, tile=8, flush=2),
+    dict(variant=6, tile=8, flush=1, split=300),
+    dict(variant=6, tile=16, wg_waves=2, flush=2, order=2, split=256),
 ]
 
 
@@ -162,6 +165,29 @@ def test_owner_tiles_weights_gains_flags(mw, npol):
     assert nl2(back, ref_back) <= TOL
 
 
+@pytest.mark.parametrize("npol", [1, 2, 4])
+def test_block_runs_equal_wave_tiles_bitwise(mw, npol):
+    """Variant 6 accumulates every (cell, py) run in the order of variant 4; its padding
+    entries add exact zeros. With weights, gains and flags its grid equals variant 4's bit for
+    bit (and so the oracle to the same tolerance), and it is reproducible."""
+    rng = np.random.default_rng(60 + npol)
+    wl = synth.mwa_scale(seed=2040 + npol, nant=48, nchan=6, ntime=2, npol=npol, n=256, nsrc=20)
+    wl.flags = (rng.random(wl.ngroups) < 0.15).astype(np.uint8)
+    wl.weights = rng.uniform(0.2, 2.0, wl.ngroups).astype(np.float32)
+    gains = synth.random_gains(wl.nant, rng)
+    v, g = to_dev(wl.vis), to_dev(gains)
+    with _plan(mw, wl, tuning=dict(variant=4, tile=8, flush=2, split=700)) as p4, \
+            _plan(mw, wl, tuning=dict(variant=6, tile=8, flush=2, split=700)) as p6:
+        assert p6.info(0)["variant"] == 6
+        a4 = to_host(p4.grid(v, gains=g))
+        a6 = to_host(p6.grid(v, gains=g))
+        b6 = to_host(p6.grid(v, gains=g))
+    np.testing.assert_array_equal(a6, a4)
+    np.testing.assert_array_equal(a6, b6)
+    ref = oracle_grid(wl, wl.vis, weights=wl.weights.astype(np.float64), gains=gains)
+    assert nl2(a6, ref) <= TOL
+
+
 def test_wave_tiles_merge_is_bit_reproducible(mw, small_mwa):
     wl = small_mwa
     with _plan(mw, wl, tuning=dict(variant=4, tile=8, flush=2), with_ants=False) as plan:
@@ -186,12 +212,12 @@ def test_grid_parity_mwa_4pol(mw, small_mwa, tuning):
 
 @pytest.mark.parametrize("npol", [1, 2, 4])
 @pytest.mark.parametrize("W", [3, 5, 7])
-@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 6])
 def test_grid_parity_variants(mw, npol, W, variant):
     wl = synth.mwa_scale(seed=2005 + W, nant=40, nchan=4, ntime=2, npol=npol, n=256, nsrc=10,
                          W=W, O=8)
     ref = oracle_grid(wl, wl.vis)
-    tile = 8 if variant == 4 else (64 if npol == 1 else 32)
+    tile = 8 if variant in (4, 6) else (64 if npol == 1 else 32)
     with _plan(mw, wl, tuning=dict(variant=variant, tile=tile, split=500),
                with_ants=False) as plan:
         got = to_host(plan.grid(to_dev(wl.vis)))

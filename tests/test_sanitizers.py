@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-sanitize-recover=all"]
 SOURCES = ["abi.cpp", "pswf.cpp", "plan.hip", "grid.hip", "degrid.hip", "image.hip", "fft.hip", "stack.hip",
-           "batched.hip", "tuner.cpp", "stokes.hip", "owner.hip", "calib.hip", "weighting.hip", "wstack.hip", "workers.cpp"]
+           "batched.hip", "tuner.cpp", "stokes.hip", "owner.hip", "calib.hip", "weighting.hip", "wstack.hip", "workers.cpp", "runs.hip"]
 
 
 def _run(cmd, **kw):
