@@ -8,8 +8,10 @@
 // is the transpose of the scatter rather than a replacement for it.
 //
 // One workgroup per work item stages the item's haloed tile of the grid in LDS (coalesced
-// loads), then each thread gathers one group. Per-antenna gradient sums accumulate in LDS
-// and are added to HBM once per workgroup.
+// loads). For supports 3, 5 and 7 the groups of one (cell, py) run share the contraction of
+// the footprint's rows, formed once per run; other supports gather each group's footprint in
+// one thread. Per-antenna gradient sums accumulate in LDS and are added to HBM once per
+// workgroup.
 #include "internal.h"
 #include "degrid_core.h"
 
@@ -25,6 +27,13 @@ template <int NPOL, int WT>
 __global__ __launch_bounds__(1024) void k_degrid(DegridArgs a) {
     extern __shared__ __align__(16) float smem[];
     degrid_item<NPOL, WT>(a, a.work[blockIdx.x], smem);
+}
+
+// Supports 3, 5 and 7: groups of one (cell, py) run share their row contraction.
+template <int NPOL, int W>
+__global__ __launch_bounds__(256) void k_degrid_runs(DegridArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    degrid_item_runs<NPOL, W>(a, a.work[blockIdx.x], smem);
 }
 
 template <int NPOL>
@@ -47,19 +56,29 @@ Status launch_degrid_npol(Instance &I, DegridArgs &a, hipStream_t s) {
     if (a.grad_gains) MWG_TRY(launch_fill_zero(a.grad_gains, sizeof(float2) * (size_t)I.nant, s));
     if (I.nwork == 0) return Status::Ok();
     const int R = I.L.tile + I.W - 1;
-    size_t lds = sizeof(float2) * (size_t)NPOL * R * R + 4 * (size_t)((I.O * I.W + 1) & ~1);
+    const int threads = degrid_threads(I.nkept, I.nwork);
+    const dim3 grid((unsigned)I.nwork), block((unsigned)threads);
     a.ant_in_lds = 0;
-    if (a.grad_gains && lds + sizeof(float2) * (size_t)I.nant <= 64 * 1024) {
-        a.ant_in_lds = 1;
-        lds += sizeof(float2) * (size_t)I.nant;
-    }
-    if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "degrid tile needs %zu B of LDS", lds);
-    const dim3 grid((unsigned)I.nwork), block((unsigned)degrid_threads(I.nkept, I.nwork));
-    switch (I.W) {  // the common supports with their taps in registers
-    case 3: hipLaunchKernelGGL((k_degrid<NPOL, 3>), grid, block, lds, s, a); break;
-    case 5: hipLaunchKernelGGL((k_degrid<NPOL, 5>), grid, block, lds, s, a); break;
-    case 7: hipLaunchKernelGGL((k_degrid<NPOL, 7>), grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL((k_degrid<NPOL, 0>), grid, block, lds, s, a); break;
+    if (I.W == 3 || I.W == 5 || I.W == 7) {
+        size_t lds = degrid_runs_lds(NPOL, I.L.tile, I.W, I.O, threads / 64, 0);
+        if (a.grad_gains && degrid_runs_lds(NPOL, I.L.tile, I.W, I.O, threads / 64, I.nant) <= 64 * 1024) {
+            a.ant_in_lds = 1;
+            lds = degrid_runs_lds(NPOL, I.L.tile, I.W, I.O, threads / 64, I.nant);
+        }
+        if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "degrid tile needs %zu B of LDS", lds);
+        switch (I.W) {
+        case 3: hipLaunchKernelGGL((k_degrid_runs<NPOL, 3>), grid, block, lds, s, a); break;
+        case 5: hipLaunchKernelGGL((k_degrid_runs<NPOL, 5>), grid, block, lds, s, a); break;
+        default: hipLaunchKernelGGL((k_degrid_runs<NPOL, 7>), grid, block, lds, s, a); break;
+        }
+    } else {
+        size_t lds = sizeof(float2) * (size_t)NPOL * R * R + 4 * (size_t)((I.O * I.W + 1) & ~1);
+        if (a.grad_gains && lds + sizeof(float2) * (size_t)I.nant <= 64 * 1024) {
+            a.ant_in_lds = 1;
+            lds += sizeof(float2) * (size_t)I.nant;
+        }
+        if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "degrid tile needs %zu B of LDS", lds);
+        hipLaunchKernelGGL((k_degrid<NPOL, 0>), grid, block, lds, s, a);
     }
     MWG_HIP(hipGetLastError());
     return Status::Ok();
