@@ -270,7 +270,10 @@ __global__ __launch_bounds__(256) void k_degrid_batched(const BatchDesc *desc, c
     a.O = O;
     a.nant = d.nant;
     a.ant_in_lds = ant_in_lds;
-    degrid_item<NPOL, WT>(a, d.work[it.item], smem);
+    if constexpr (NPOL == 4 && WT > 0)
+        degrid_item_runs<NPOL, WT>(a, d.work[it.item], smem);
+    else
+        degrid_item<NPOL, WT>(a, d.work[it.item], smem);
 }
 
 int plane2(int R, int STR, int W) {
@@ -627,9 +630,16 @@ Status batch_prepare(Plan &P, hipStream_t s) {
     B->grid_lds = 4 * ((size_t)B->O * 8 + (size_t)B->waves * B->per_wave);
     B->grid_blocks = std::max(1, (B->nitems + B->waves - 1) / B->waves);
     const int Rd = B->T + B->W - 1;
-    B->degrid_lds = sizeof(float2) * (size_t)B->npol * Rd * Rd + 4 * (size_t)((B->O * B->W + 1) & ~1);
-    B->ant_in_lds = (max_nant > 0 && B->degrid_lds + sizeof(float2) * (size_t)max_nant <= 64 * 1024) ? 1 : 0;
-    if (B->ant_in_lds) B->degrid_lds += sizeof(float2) * (size_t)max_nant;
+    if (B->npol == 4 && (B->W == 3 || B->W == 5 || B->W == 7)) {  // the run degridder
+        const int nw = B->dthreads / 64;
+        B->degrid_lds = degrid_runs_lds(B->npol, B->T, B->W, B->O, nw, 0);
+        B->ant_in_lds = (max_nant > 0 && degrid_runs_lds(B->npol, B->T, B->W, B->O, nw, max_nant) <= 64 * 1024) ? 1 : 0;
+        if (B->ant_in_lds) B->degrid_lds = degrid_runs_lds(B->npol, B->T, B->W, B->O, nw, max_nant);
+    } else {
+        B->degrid_lds = sizeof(float2) * (size_t)B->npol * Rd * Rd + 4 * (size_t)((B->O * B->W + 1) & ~1);
+        B->ant_in_lds = (max_nant > 0 && B->degrid_lds + sizeof(float2) * (size_t)max_nant <= 64 * 1024) ? 1 : 0;
+        if (B->ant_in_lds) B->degrid_lds += sizeof(float2) * (size_t)max_nant;
+    }
     return Status::Ok();
 }
 

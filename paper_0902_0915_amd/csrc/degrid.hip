@@ -8,9 +8,9 @@
 // is the transpose of the scatter rather than a replacement for it.
 //
 // One workgroup per work item stages the item's haloed tile of the grid in LDS (coalesced
-// loads). For supports 3, 5 and 7 the groups of one (cell, py) run share the contraction of
-// the footprint's rows, formed once per run; other supports gather each group's footprint in
-// one thread. Per-antenna gradient sums accumulate in LDS and are added to HBM once per
+// loads). With four polarisations and supports 3, 5 and 7 the groups of one (cell, py) run
+// share the contraction of the footprint's rows, formed once per run; otherwise each thread
+// gathers one group's footprint. Per-antenna gradient sums accumulate in LDS and are added to HBM once per
 // workgroup.
 #include "internal.h"
 #include "degrid_core.h"
@@ -29,7 +29,10 @@ __global__ __launch_bounds__(1024) void k_degrid(DegridArgs a) {
     degrid_item<NPOL, WT>(a, a.work[blockIdx.x], smem);
 }
 
-// Supports 3, 5 and 7: groups of one (cell, py) run share their row contraction.
+// Four polarisations, supports 3, 5 and 7: groups of one (cell, py) run share their row
+// contraction. (With one or two polarisations a group's own footprint read is short and the
+// per-run bookkeeping costs more than it saves: the 96-job single-polarisation batch took
+// 1.40 ms with the per-group form and 1.63 ms with runs.)
 template <int NPOL, int W>
 __global__ __launch_bounds__(256) void k_degrid_runs(DegridArgs a) {
     extern __shared__ __align__(16) float smem[];
@@ -59,7 +62,7 @@ Status launch_degrid_npol(Instance &I, DegridArgs &a, hipStream_t s) {
     const int threads = degrid_threads(I.nkept, I.nwork);
     const dim3 grid((unsigned)I.nwork), block((unsigned)threads);
     a.ant_in_lds = 0;
-    if (I.W == 3 || I.W == 5 || I.W == 7) {
+    if (NPOL == 4 && (I.W == 3 || I.W == 5 || I.W == 7)) {
         size_t lds = degrid_runs_lds(NPOL, I.L.tile, I.W, I.O, threads / 64, 0);
         if (a.grad_gains && degrid_runs_lds(NPOL, I.L.tile, I.W, I.O, threads / 64, I.nant) <= 64 * 1024) {
             a.ant_in_lds = 1;
@@ -78,7 +81,12 @@ Status launch_degrid_npol(Instance &I, DegridArgs &a, hipStream_t s) {
             lds += sizeof(float2) * (size_t)I.nant;
         }
         if (lds > 160 * 1024) return make_error(MW_ERR_UNSUPPORTED, "degrid tile needs %zu B of LDS", lds);
-        hipLaunchKernelGGL((k_degrid<NPOL, 0>), grid, block, lds, s, a);
+        switch (I.W) {  // the common supports with their taps in registers
+        case 3: hipLaunchKernelGGL((k_degrid<NPOL, 3>), grid, block, lds, s, a); break;
+        case 5: hipLaunchKernelGGL((k_degrid<NPOL, 5>), grid, block, lds, s, a); break;
+        case 7: hipLaunchKernelGGL((k_degrid<NPOL, 7>), grid, block, lds, s, a); break;
+        default: hipLaunchKernelGGL((k_degrid<NPOL, 0>), grid, block, lds, s, a); break;
+        }
     }
     MWG_HIP(hipGetLastError());
     return Status::Ok();
