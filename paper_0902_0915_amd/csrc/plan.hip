@@ -204,8 +204,10 @@ __global__ void k_positions(PosArgs a) {
     int status = 3; // 0 kept, 1 flagged, 2 outside, 3 out of range
     if (g < a.ngroups) {
         uint32_t packed = kDropped;
-        const int64_t r = g / a.nchan;
-        const int ch = (int)(g - r * a.nchan);
+        // 32-bit integer work throughout: groups < 2^31 (checked when the plan is built)
+        const uint32_t g32 = (uint32_t)g, nc = (uint32_t)a.nchan;
+        const int64_t r = (int64_t)(g32 / nc);
+        const int ch = (int)(g32 - (uint32_t)r * nc);
         const double f = a.freq[ch];
         bool deselected = false;
         if (a.wsel) {
@@ -222,13 +224,16 @@ __global__ void k_positions(PosArgs a) {
             const double qxd = floor(x * (double)a.O + 0.5);
             const double qyd = floor(y * (double)a.O + 0.5);
             status = 2;
-            if (fabs(qxd) < 1e15 && fabs(qyd) < 1e15) {
-                const int64_t qx = (int64_t)qxd, qy = (int64_t)qyd;
-                const int64_t half = a.O / 2;
-                int64_t cx = (qx + half) / a.O, cy = (qy + half) / a.O;
+            // |q| >= 2^24 puts the cell more than 2^20 - 1 cells from the centre (O <= 16),
+            // outside any grid of at most 4096 cells: such groups (and NaN) are outside
+            // without the integer steps, which then fit 32 bits
+            if (fabs(qxd) < 16777216.0 && fabs(qyd) < 16777216.0) {
+                const int qx = (int)qxd, qy = (int)qyd;
+                const int half = a.O / 2;
+                int cx = (qx + half) / a.O, cy = (qy + half) / a.O;
                 if ((qx + half) % a.O != 0 && (qx + half) < 0) cx -= 1; // floor division
                 if ((qy + half) % a.O != 0 && (qy + half) < 0) cy -= 1;
-                const int64_t px = qx - cx * a.O, py = qy - cy * a.O;
+                const int px = qx - cx * a.O, py = qy - cy * a.O;
                 const int h = a.kidx ? (a.ksup[a.kidx[g]] - 1) / 2 : a.h;
                 if (cx - h >= 0 && cx + h < a.nx && cy - h >= 0 && cy + h < a.ny) {
                     packed = pack_pos((int)cx, (int)cy, (int)(px + half), (int)(py + half));
@@ -258,11 +263,13 @@ __global__ void k_positions(PosArgs a) {
     }
 }
 
-// Sums the per-block counts: one workgroup, out[c] = sum over blocks of cnt[b][c].
+// Sums the per-block counts: out[c] += sum over blocks of cnt[b][c] (out zeroed before),
+// a grid-stride sum per workgroup and three atomics per workgroup.
+constexpr int kSumBlocks = 128;
 __global__ void k_sum_counts(const uint32_t *cnt, int64_t nblocks, unsigned long long *out) {
     __shared__ unsigned long long part[kBlock / 64][3];
     unsigned long long t[3] = {0, 0, 0};
-    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x)
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += (int64_t)gridDim.x * blockDim.x)
         for (int c = 0; c < 3; c++) t[c] += cnt[b * 3 + c];
     for (int c = 0; c < 3; c++) {
         unsigned long long v = t[c];
@@ -273,7 +280,7 @@ __global__ void k_sum_counts(const uint32_t *cnt, int64_t nblocks, unsigned long
     if (threadIdx.x < 3) {
         unsigned long long v = 0;
         for (int k = 0; k < kBlock / 64; k++) v += part[k][threadIdx.x];
-        out[threadIdx.x] = v;
+        if (v) atomicAdd(&out[threadIdx.x], v);
     }
 }
 
@@ -342,8 +349,19 @@ __device__ inline uint32_t radial_rank(uint32_t cx, uint32_t cy, int tb, int nx,
     return rank;
 }
 
+// radial_rank of every cell of every tile, tile-major (T <= 16, so a rank fits a byte): for
+// plans with more groups than cells, computed once per cell instead of once per group.
+__global__ void k_rank_table(int tb, int ntx, int64_t ncells, int nx, int ny, uint8_t *ranks) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    const int64_t tile = g >> (2 * tb);
+    const uint32_t c = (uint32_t)(g & ((1 << (2 * tb)) - 1)), mask = (1u << tb) - 1u;
+    const uint32_t cx = ((uint32_t)(tile % ntx) << tb) | (c & mask), cy = ((uint32_t)(tile / ntx) << tb) | (c >> tb);
+    ranks[g] = (uint8_t)radial_rank(cx, cy, tb, nx, ny);
+}
+
 __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int nx, int ny, int order,
-                       uint32_t sentinel, uint32_t *keys) {
+                       uint32_t sentinel, const uint8_t *ranks, uint32_t *keys) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const uint32_t p = pos[g];
@@ -360,7 +378,7 @@ __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int nx, 
             // of one baseline fall on radially neighbouring cells, which this makes
             // consecutive.
             uint32_t cell = ((cy & mask) << tb) | (cx & mask);
-            if (order == 3) cell = radial_rank(cx, cy, tb, nx, ny);
+            if (order == 3) cell = ranks ? (uint32_t)ranks[((size_t)tile << (2 * tb)) | cell] : radial_rank(cx, cy, tb, nx, ny);
             k = (tile << (2 * tb + 4)) | (cell << 4) | (p >> 28);
         }
     }
@@ -372,7 +390,8 @@ __global__ void k_keys(const uint32_t *pos, int64_t n, int tb, int ntx, int nx, 
 //   hist:    per block digit counts, stored digit-major [256][nblocks]
 //   scan:    exclusive prefix over that array -> each (digit, block) output base
 //   scatter: each block ranks its keys stably (wave ballots for equal digits, waves in
-//            order) and writes them at base + rank.
+//            order), places them in LDS in digit order, then writes each digit's run to
+//            consecutive positions from its output base.
 // ------------------------------------------------------------------------------------------
 constexpr int kSortItems = 16;                 // keys per thread per block
 constexpr int kSortChunk = kBlock * kSortItems; // keys per block
@@ -390,21 +409,40 @@ __global__ void k_rs_hist(const uint32_t *keys, int64_t n, int shift, uint32_t *
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
-                             uint32_t *vals_out, const uint32_t *offsets, int64_t n, int shift,
-                             int nblocks) {
-    __shared__ uint32_t run[256];
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
+                                                     uint32_t *keys_out, uint32_t *vals_out,
+                                                     const uint32_t *offsets, int64_t n, int shift, int nblocks) {
+    __shared__ uint32_t gbase[256], lstart[256], run[256], wsum[kBlock / 64];
     __shared__ uint32_t wcnt[kBlock / 64][256];
+    __shared__ uint32_t stk[kSortChunk], stv[kSortChunk];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    run[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+    // this block's count of digit tid, from the scanned digit-major (digit, block) array
+    const int64_t idx = (int64_t)tid * nblocks + blockIdx.x;
+    const uint32_t off = offsets[idx];
+    const uint32_t cnt = (idx + 1 < (int64_t)256 * nblocks ? offsets[idx + 1] : (uint32_t)n) - off;
+    uint32_t inc = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int w = 0; w < wave; w++) wb += wsum[w];
+    gbase[tid] = off;
+    lstart[tid] = wb + inc - cnt;
+    run[tid] = wb + inc - cnt;
     for (int w = 0; w < kBlock / 64; w++) wcnt[w][tid] = 0;
     __syncthreads();
+    // stable ranks within the block (items in order, waves in order, lanes in order): each
+    // key is placed in LDS at its digit's local start plus its rank
     const int64_t base = (int64_t)blockIdx.x * kSortChunk;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int it = 0; it < kSortItems; it++) {
         const int64_t i = base + (int64_t)it * kBlock + tid;
         const bool valid = i < n;
         const uint32_t k = valid ? keys_in[i] : 0u;
+        const uint32_t v = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
         const uint32_t d = (k >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
         for (int b = 0; b < 8; b++) {
@@ -416,10 +454,10 @@ __global__ void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in, u
         if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t off = run[d] + (uint32_t)rank;
-            for (int w = 0; w < wave; w++) off += wcnt[w][d];
-            keys_out[off] = k;
-            vals_out[off] = vals_in ? vals_in[i] : (uint32_t)i;
+            uint32_t pos = run[d] + (uint32_t)rank;
+            for (int w = 0; w < wave; w++) pos += wcnt[w][d];
+            stk[pos] = k;
+            stv[pos] = v;
         }
         __syncthreads();
         uint32_t tot = 0;
@@ -429,6 +467,14 @@ __global__ void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in, u
         }
         run[tid] += tot;
         __syncthreads();
+    }
+    // the staged keys in digit order: each digit's run goes to consecutive global positions
+    const int nvalid = (int)((n - base) < kSortChunk ? (n - base) : kSortChunk);
+    for (int j = tid; j < nvalid; j += kBlock) {
+        const uint32_t k = stk[j], d = (k >> shift) & 255u;
+        const uint32_t g = gbase[d] + ((uint32_t)j - lstart[d]);
+        keys_out[g] = k;
+        vals_out[g] = stv[j];
     }
 }
 
@@ -671,8 +717,18 @@ Status rebuild_schedule(Instance &I, const Launch &L, hipStream_t s) {
         MWG_TRY(vals2.alloc(4 * ng, s));
         uint32_t *skeys = nullptr, *sperm = nullptr;
         if (ng > 0) {
+            // radial ranks from a per-cell table when there are more groups than cells
+            Tmp ranks;
+            const int64_t ncells = ntiles << (2 * tb);
+            const bool table = L.order == 3 && tb <= 4 && ng > ncells;
+            if (table) {
+                MWG_TRY(ranks.alloc((size_t)ncells, s));
+                hipLaunchKernelGGL(k_rank_table, dim3(grid1d(ncells)), dim3(kBlock), 0, s, tb, ntx, ncells, I.nx,
+                                   I.ny, ranks.as<uint8_t>());
+                MWG_HIP(hipGetLastError());
+            }
             hipLaunchKernelGGL(k_keys, dim3(grid1d(ng)), dim3(kBlock), 0, s, I.pos, ng, tb, ntx, I.nx, I.ny, L.order,
-                               sentinel, keys.as<uint32_t>());
+                               sentinel, table ? ranks.as<uint8_t>() : (const uint8_t *)nullptr, keys.as<uint32_t>());
             MWG_HIP(hipGetLastError());
             MWG_TRY(radix_sort(keys.as<uint32_t>(), keys2.as<uint32_t>(), vals.as<uint32_t>(),
                                vals2.as<uint32_t>(), ng, keybits, &skeys, &sperm, s));
@@ -1114,7 +1170,8 @@ Status build_instance(Instance &I, const mw_instance &d, const mw_tuning *tuning
     if (ng > 0) {
         hipLaunchKernelGGL(k_positions, dim3(grid1d(ng)), dim3(kBlock), 0, s, a);
         MWG_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(kBlock), 0, s, a.blk_counts, pos_blocks,
+        const unsigned sb = (unsigned)std::min<int64_t>(kSumBlocks, (pos_blocks + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_sum_counts, dim3(sb), dim3(kBlock), 0, s, a.blk_counts, pos_blocks,
                            counts.as<unsigned long long>());
         MWG_HIP(hipGetLastError());
     }
