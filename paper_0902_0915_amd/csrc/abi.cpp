@@ -184,7 +184,10 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
             if (!s.ok()) return fail(s);
         }
         hipStream_t st = (hipStream_t)stream;
-        mwg::TmpScope scratch(st);  // the build's temporaries, freed after the last sync below
+        size_t tmp_hint = 0;  // the largest instance's build in one temporary block
+        for (int i = 0; i < ninst; i++)
+            tmp_hint = std::max(tmp_hint, mwg::plan_tmp_hint(inst[i].nrow * (int64_t)inst[i].nchan, inst[i].nx, inst[i].ny));
+        mwg::TmpScope scratch(st, tmp_hint);  // the build's temporaries, freed after the last sync below
         mwg::Plan *P = new mwg::Plan();
         if (hipGetDevice(&P->device) != hipSuccess) {
             delete P;
@@ -201,7 +204,7 @@ mw_status mw_grid_plan(mw_plan *out, const mw_instance *inst, int32_t ninst, con
             };
             mwg::Status s;
             if (ninst >= kParallelPlan) {
-                s = mwg::parallel_instances(P->device, ninst, st, build);
+                s = mwg::parallel_instances(P->device, ninst, st, build, tmp_hint);
             } else {
                 for (int i = 0; i < ninst && s.ok(); i++) s = build(i, st);
             }

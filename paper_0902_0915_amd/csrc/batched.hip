@@ -479,7 +479,9 @@ Status batch_prepare(Plan &P, hipStream_t s) {
         return Status::Ok();
     };
     if (n >= 4) {
-        MWG_TRY(parallel_instances(P.device, n, s, prepare));
+        size_t hint = 0;
+        for (const Instance *I : P.inst) hint = std::max(hint, plan_tmp_hint(I->ngroups, I->nx, I->ny));
+        MWG_TRY(parallel_instances(P.device, n, s, prepare, hint));
     } else {
         for (int i = 0; i < n; i++) MWG_TRY(prepare(i, s));
     }

@@ -73,7 +73,9 @@ struct DevTmp {
 
 class TmpScope {
   public:
-    explicit TmpScope(hipStream_t s);
+    // first_block: size of the pool's first block (0: the default); a build that knows its
+    // peak need gets it in one allocation (each hipMalloc/hipFree pair costs ~0.3 ms)
+    explicit TmpScope(hipStream_t s, size_t first_block = 0);
     ~TmpScope();
     TmpScope(const TmpScope &) = delete;
     TmpScope &operator=(const TmpScope &) = delete;
@@ -86,7 +88,11 @@ class TmpScope {
 // of its own that first waits for the work already on `after`, each with its own pool of
 // temporaries (workers.cpp). Jobs must touch disjoint state. Returns the first error; all
 // device work of the jobs has finished when it returns.
-Status parallel_instances(int device, int n, hipStream_t after, const std::function<Status(int, hipStream_t)> &job);
+Status parallel_instances(int device, int n, hipStream_t after, const std::function<Status(int, hipStream_t)> &job,
+                          size_t tmp_first_block = 0);
+// A first temporary block that holds one instance's build: its sort (16 bytes per group and
+// a little more) and the per-cell tables of its grid.
+size_t plan_tmp_hint(int64_t ngroups, int nx, int ny);
 
 // Smallest r with 2^r >= v (the exponent of a power-of-two tile size).
 inline int ilog2(int v) {

@@ -87,6 +87,7 @@ struct TmpPool {
         bool freed;
     };
     hipStream_t stream = nullptr;
+    size_t first = 0;  // size of the first block (0: kTmpBlock)
     std::vector<Block> blocks;
     std::vector<Rec> stack;
 
@@ -95,7 +96,7 @@ struct TmpPool {
         int b = stack.empty() ? 0 : stack.back().block;  // blocks after b are empty
         while (b < (int)blocks.size() && blocks[b].size - blocks[b].top < nbytes) b++;
         if (b == (int)blocks.size()) {
-            size_t want = kTmpBlock;
+            size_t want = blocks.empty() ? std::max(kTmpBlock, first) : kTmpBlock;
             for (const Block &k : blocks) want = std::max(want, 2 * k.size);
             want = std::max(want, nbytes);
             void *q = nullptr;
@@ -156,11 +157,16 @@ void DevTmp::release() {
     pool = nullptr;
 }
 
-TmpScope::TmpScope(hipStream_t s) {
+TmpScope::TmpScope(hipStream_t s, size_t first_block) {
     if (t_tmp_pool) return;
     own = new TmpPool();
     own->stream = s;
+    own->first = first_block;
     t_tmp_pool = own;
+}
+
+size_t plan_tmp_hint(int64_t ngroups, int nx, int ny) {
+    return 17 * (size_t)std::max<int64_t>(ngroups, 0) + 2 * (size_t)nx * (size_t)ny + (size_t(4) << 20);
 }
 
 TmpScope::~TmpScope() {

@@ -15,7 +15,8 @@ namespace {
 constexpr int kPlanThreads = 8;
 }
 
-Status parallel_instances(int device, int n, hipStream_t after, const std::function<Status(int, hipStream_t)> &job) {
+Status parallel_instances(int device, int n, hipStream_t after, const std::function<Status(int, hipStream_t)> &job,
+                          size_t tmp_first_block) {
     if (n <= 0) return Status::Ok();
     const int nt = std::min(kPlanThreads, n);
     hipEvent_t ready = nullptr;
@@ -43,7 +44,7 @@ Status parallel_instances(int device, int n, hipStream_t after, const std::funct
                 out = make_error(MW_ERR_HIP, "hipStreamWaitEvent failed");
                 failed = true;
             } else {
-                TmpScope scope(s);  // this thread's temporaries; waits for s when it ends
+                TmpScope scope(s, tmp_first_block);  // this thread's temporaries; waits for s when it ends
                 for (int i = next++; i < n && !failed; i = next++) {
                     Status r = job(i, s);
                     if (!r.ok()) {
