@@ -439,7 +439,69 @@ Status iterate(Instance &I, float2 *g, int niter, float *rel, hipStream_t s) {
     return Status::Ok();
 }
 
+// Antenna-pair lists on the device (up to 2048 antennas: a dense table of pair keys
+// a1 * nant + a2). The pairs are numbered in order of their first row: each key's first row by
+// an atomic minimum, then a scan over the rows that are first of their key.
+__global__ void k_pair_first(const int32_t *a1, const int32_t *a2, int64_t nrow, int nant, uint32_t *first) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrow) atomicMin(&first[(uint32_t)a1[r] * (uint32_t)nant + (uint32_t)a2[r]], (uint32_t)r);
+}
+
+__global__ void k_pair_flag(const int32_t *a1, const int32_t *a2, int64_t nrow, int nant, const uint32_t *first,
+                            uint32_t *flag) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrow) flag[r] = first[(uint32_t)a1[r] * (uint32_t)nant + (uint32_t)a2[r]] == (uint32_t)r ? 1u : 0u;
+}
+
+// pair of every row; the first row of each pair writes the pair's antennas
+__global__ void k_pair_ids(const int32_t *a1, const int32_t *a2, int64_t nrow, int nant, const uint32_t *first,
+                           const uint32_t *scan, uint32_t *pair_of, uint32_t *pant) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrow) return;
+    const uint32_t f = first[(uint32_t)a1[r] * (uint32_t)nant + (uint32_t)a2[r]], pid = scan[f];
+    pair_of[r] = pid;
+    if (f == (uint32_t)r) pant[pid] = (uint32_t)a1[r] | (uint32_t)a2[r] << 16;
+}
+
+// first index of every pair in the pair-sorted rows (every pair has a row), and the end
+__global__ void k_pair_starts(const uint32_t *skeys, int64_t n, int64_t npair, int32_t *pstart) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0 || skeys[i - 1] != skeys[i]) pstart[skeys[i]] = (int32_t)i;
+    if (i == n - 1) pstart[npair] = (int32_t)n;
+}
+
+// entry e = pair << 1 | side belongs to the pair's first (side 0) or second antenna
+__global__ void k_ant_keys(const uint32_t *pant, int64_t nent, uint32_t *keys, uint32_t *counts) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nent) return;
+    const uint32_t p = pant[e >> 1], a = (e & 1) ? p >> 16 : p & 0xFFFFu;
+    keys[e] = a;
+    atomicAdd(&counts[a], 1u);
+}
+
+__global__ void k_ant_lists(const uint32_t *sorted_e, const uint32_t *pant, int64_t nent, int32_t *entry,
+                            int32_t *partner) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nent) return;
+    const uint32_t e = sorted_e[k], p = pant[e >> 1];
+    entry[k] = (int32_t)e;
+    partner[k] = (int32_t)((e & 1) ? (p & 0xFFFFu) : (p >> 16));
+}
+
+int bits_for(uint64_t maxval) {
+    int r = 1;
+    while (r < 32 && (maxval >> r) != 0) r++;
+    return r;
+}
+
 } // namespace
+
+Status sort_pairs(uint32_t *keys, uint32_t *keys_alt, const uint32_t *vals_init, uint32_t *vals,
+                  uint32_t *vals_alt, int64_t n, int keybits, uint32_t **keys_out, uint32_t **vals_out,
+                  hipStream_t s);
+Status exclusive_scan_u32(uint32_t *data, int64_t n, hipStream_t s);
+Status launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
 Status stage_sources(Instance &I, const double *sources, int nsrc, bool from_host, hipStream_t s);
 
@@ -460,38 +522,112 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
     MWG_HIP(hipGetLastError());
     if (!I.has_ants) return Status::Ok();
     if (I.nrow >= (int64_t)1 << 30) return make_error(MW_ERR_UNSUPPORTED, "calibration lists need nrow < 2^30");
+    auto alloc_lists = [&](int64_t npair) -> Status {
+        I.cal_npair = npair;
+        MWG_TRY(I.arena.alloc(&p, 4 * ((size_t)I.nant + 1)));
+        I.cal_start = (int32_t *)p;
+        MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(2 * (size_t)npair, 1)));
+        I.cal_entry = (int32_t *)p;
+        MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(2 * (size_t)npair, 1)));
+        I.cal_partner = (int32_t *)p;
+        MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>((size_t)npair, 1)));
+        I.cal_pant = (uint32_t *)p;
+        MWG_TRY(I.arena.alloc(&p, 4 * ((size_t)npair + 1)));
+        I.cal_pstart = (int32_t *)p;
+        MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>((size_t)I.nrow, 1)));
+        I.cal_prows = (int32_t *)p;
+        MWG_TRY(I.arena.alloc(&p, sizeof(float4) * (size_t)std::max<int64_t>(npair, 1)));
+        I.cal_pq = (float4 *)p;
+        MWG_TRY(I.arena.alloc(&p, sizeof(float2) * (size_t)I.nant));
+        I.cal_g = (float2 *)p;
+        MWG_TRY(I.arena.alloc(&p, sizeof(double) * 2 * (size_t)I.nant));
+        I.cal_red = (double *)p;
+        return Status::Ok();
+    };
+    const int64_t nn = (int64_t)I.nant * I.nant;
+    if (nn <= ((int64_t)1 << 22)) {
+        // on the device: pair numbers, each pair's rows (a stable sort of the rows by pair) and
+        // each antenna's pairs (a stable sort of the entries by antenna), as the host lists
+        // below would give them
+        const int64_t nrow = I.nrow;
+        if (nrow == 0) {
+            MWG_TRY(alloc_lists(0));
+            MWG_TRY(launch_fill_u32((uint32_t *)I.cal_start, I.nant + 1, 0u, s));
+            MWG_TRY(launch_fill_u32((uint32_t *)I.cal_pstart, 1, 0u, s));
+            return Status::Ok();
+        }
+        DevTmp first, flag;
+        MWG_TRY(first.alloc(4 * (size_t)nn, s));
+        MWG_TRY(flag.alloc(4 * ((size_t)nrow + 1), s));
+        MWG_TRY(launch_fill_u32(first.as<uint32_t>(), nn, 0xFFFFFFFFu, s));
+        MWG_TRY(launch_fill_u32(flag.as<uint32_t>() + nrow, 1, 0u, s));
+        hipLaunchKernelGGL(k_pair_first, dim3(grid1d(nrow)), dim3(kBlock), 0, s, a1_dev, a2_dev, nrow, I.nant,
+                           first.as<uint32_t>());
+        hipLaunchKernelGGL(k_pair_flag, dim3(grid1d(nrow)), dim3(kBlock), 0, s, a1_dev, a2_dev, nrow, I.nant,
+                           first.as<uint32_t>(), flag.as<uint32_t>());
+        MWG_HIP(hipGetLastError());
+        MWG_TRY(exclusive_scan_u32(flag.as<uint32_t>(), nrow + 1, s));
+        uint32_t hnpair = 0;
+        MWG_HIP(hipMemcpyAsync(&hnpair, flag.as<uint32_t>() + nrow, 4, hipMemcpyDeviceToHost, s));
+        MWG_HIP(hipStreamSynchronize(s));
+        const int64_t npair = hnpair;
+        MWG_TRY(alloc_lists(npair));
+        // rows of each pair
+        DevTmp keys, keys2, vals, vals2;
+        MWG_TRY(keys.alloc(4 * (size_t)nrow, s));
+        MWG_TRY(keys2.alloc(4 * (size_t)nrow, s));
+        MWG_TRY(vals.alloc(4 * (size_t)nrow, s));
+        MWG_TRY(vals2.alloc(4 * (size_t)nrow, s));
+        hipLaunchKernelGGL(k_pair_ids, dim3(grid1d(nrow)), dim3(kBlock), 0, s, a1_dev, a2_dev, nrow, I.nant,
+                           first.as<uint32_t>(), flag.as<uint32_t>(), keys.as<uint32_t>(), I.cal_pant);
+        MWG_HIP(hipGetLastError());
+        uint32_t *sk = nullptr, *sv = nullptr;
+        MWG_TRY(sort_pairs(keys.as<uint32_t>(), keys2.as<uint32_t>(), nullptr, vals.as<uint32_t>(),
+                           vals2.as<uint32_t>(), nrow, bits_for((uint64_t)npair - 1), &sk, &sv, s));
+        MWG_HIP(hipMemcpyAsync(I.cal_prows, sv, 4 * (size_t)nrow, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_pair_starts, dim3(grid1d(nrow)), dim3(kBlock), 0, s, sk, nrow, npair, I.cal_pstart);
+        MWG_HIP(hipGetLastError());
+        // pairs of each antenna
+        const int64_t nent = 2 * npair;
+        DevTmp ek, ek2, ev, ev2, counts;
+        MWG_TRY(ek.alloc(4 * (size_t)nent, s));
+        MWG_TRY(ek2.alloc(4 * (size_t)nent, s));
+        MWG_TRY(ev.alloc(4 * (size_t)nent, s));
+        MWG_TRY(ev2.alloc(4 * (size_t)nent, s));
+        MWG_TRY(counts.alloc(4 * ((size_t)I.nant + 1), s));
+        MWG_TRY(launch_fill_u32(counts.as<uint32_t>(), I.nant + 1, 0u, s));
+        hipLaunchKernelGGL(k_ant_keys, dim3(grid1d(nent)), dim3(kBlock), 0, s, I.cal_pant, nent, ek.as<uint32_t>(),
+                           counts.as<uint32_t>());
+        MWG_HIP(hipGetLastError());
+        MWG_TRY(exclusive_scan_u32(counts.as<uint32_t>(), I.nant + 1, s));
+        MWG_HIP(hipMemcpyAsync(I.cal_start, counts.p, 4 * ((size_t)I.nant + 1), hipMemcpyDeviceToDevice, s));
+        uint32_t *esk = nullptr, *esv = nullptr;
+        MWG_TRY(sort_pairs(ek.as<uint32_t>(), ek2.as<uint32_t>(), nullptr, ev.as<uint32_t>(), ev2.as<uint32_t>(),
+                           nent, bits_for((uint64_t)I.nant - 1), &esk, &esv, s));
+        hipLaunchKernelGGL(k_ant_lists, dim3(grid1d(nent)), dim3(kBlock), 0, s, esv, I.cal_pant, nent, I.cal_entry,
+                           I.cal_partner);
+        MWG_HIP(hipGetLastError());
+        if (!first.pooled()) MWG_HIP(hipStreamSynchronize(s));  // temporaries outlive the kernels
+        return Status::Ok();
+    }
     std::vector<int32_t> h1((size_t)I.nrow), h2((size_t)I.nrow);
     if (I.nrow > 0) {
         MWG_HIP(hipMemcpyAsync(h1.data(), a1_dev, 4 * (size_t)I.nrow, hipMemcpyDeviceToHost, s));
         MWG_HIP(hipMemcpyAsync(h2.data(), a2_dev, 4 * (size_t)I.nrow, hipMemcpyDeviceToHost, s));
     }
     MWG_HIP(hipStreamSynchronize(s));
-    // pair of every row (a dense table of antenna pairs up to 2048 antennas, else a hash map)
+    // more than 2048 antennas: the pair of every row from a hash map, on the host
     std::vector<int32_t> pair_of((size_t)I.nrow);
     std::vector<uint32_t> pant;
     {
-        const int64_t nn = (int64_t)I.nant * I.nant;
-        if (nn <= ((int64_t)1 << 22)) {
-            std::vector<int32_t> id((size_t)std::max<int64_t>(nn, 1), -1);
-            for (int64_t r = 0; r < I.nrow; r++) {
-                int32_t &x = id[(size_t)h1[r] * I.nant + h2[r]];
-                if (x < 0) {
-                    x = (int32_t)pant.size();
-                    pant.push_back((uint32_t)h1[r] | (uint32_t)h2[r] << 16);
-                }
-                pair_of[r] = x;
-            }
-        } else {
-            std::unordered_map<uint64_t, int32_t> id;
-            for (int64_t r = 0; r < I.nrow; r++) {
-                auto ins = id.emplace((uint64_t)h1[r] << 32 | (uint32_t)h2[r], (int32_t)pant.size());
-                if (ins.second) pant.push_back((uint32_t)h1[r] | (uint32_t)h2[r] << 16);
-                pair_of[r] = ins.first->second;
-            }
+        std::unordered_map<uint64_t, int32_t> id;
+        for (int64_t r = 0; r < I.nrow; r++) {
+            auto ins = id.emplace((uint64_t)h1[r] << 32 | (uint32_t)h2[r], (int32_t)pant.size());
+            if (ins.second) pant.push_back((uint32_t)h1[r] | (uint32_t)h2[r] << 16);
+            pair_of[r] = ins.first->second;
         }
     }
     const int64_t npair = (int64_t)pant.size();
-    I.cal_npair = npair;
     // rows of each pair
     std::vector<int32_t> pstart((size_t)npair + 1, 0), prows((size_t)I.nrow);
     for (int64_t r = 0; r < I.nrow; r++) pstart[pair_of[r] + 1]++;
@@ -517,24 +653,7 @@ Status build_calibration(Instance &I, const double *uvw_dev, const double *freq_
             entry[fill[a2]++] = (int32_t)(b << 1 | 1);
         }
     }
-    MWG_TRY(I.arena.alloc(&p, 4 * start.size()));
-    I.cal_start = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(entry.size(), 1)));
-    I.cal_entry = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(partner.size(), 1)));
-    I.cal_partner = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(pant.size(), 1)));
-    I.cal_pant = (uint32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * pstart.size()));
-    I.cal_pstart = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, 4 * std::max<size_t>(prows.size(), 1)));
-    I.cal_prows = (int32_t *)p;
-    MWG_TRY(I.arena.alloc(&p, sizeof(float4) * (size_t)std::max<int64_t>(npair, 1)));
-    I.cal_pq = (float4 *)p;
-    MWG_TRY(I.arena.alloc(&p, sizeof(float2) * (size_t)I.nant));
-    I.cal_g = (float2 *)p;
-    MWG_TRY(I.arena.alloc(&p, sizeof(double) * 2 * (size_t)I.nant));
-    I.cal_red = (double *)p;
+    MWG_TRY(alloc_lists(npair));
     MWG_HIP(hipMemcpyAsync(I.cal_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice, s));
     MWG_HIP(hipMemcpyAsync(I.cal_pstart, pstart.data(), 4 * pstart.size(), hipMemcpyHostToDevice, s));
     if (npair > 0) {

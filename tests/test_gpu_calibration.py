@@ -91,6 +91,27 @@ def test_solve_gains_parity_with_weights(mw, small):
         assert abs(rel - rel_ref) <= 1e-3 * rel_ref + 1e-6, (niter, rel, rel_ref)
 
 
+def test_solve_gains_rows_in_any_order(mw, small):
+    """The plan's antenna-pair lists (pairs numbered by first row, each pair's rows, each
+    antenna's pairs) for rows in random order, with rows of one pair far apart: the solve still
+    matches the oracle's StEFCal on the same rows."""
+    import dataclasses
+    rng = np.random.default_rng(8)
+    perm = rng.permutation(small.nrow)
+    wl = dataclasses.replace(small, uvw=small.uvw[perm], ant1=small.ant1[perm], ant2=small.ant2[perm])
+    M = orc.predict(wl.uvw, wl.freq, _catalogue(rng, 8))
+    rows = np.arange(wl.ngroups) // wl.nchan
+    g_true = synth.random_gains(wl.nant, rng).astype(np.complex128)
+    V = (g_true[wl.ant1[rows]] * np.conj(g_true[wl.ant2[rows]]))[:, None] * M
+    V = V + 0.2 * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    g_ref, rel_ref = orc.stefcal(V, M, wl.ant1, wl.ant2, wl.nant, wl.nchan, niter=6)
+    with _plan(mw, wl) as plan:
+        g, rel = plan.solve_gains(to_dev(V.astype(np.complex64)), to_dev(M.astype(np.complex64)), niter=6)
+        g, rel = to_host(g), float(to_host(rel)[0])
+    assert nl2(g, g_ref) <= GTOL, nl2(g, g_ref)
+    assert abs(rel - rel_ref) <= 1e-3 * rel_ref + 1e-6, (rel, rel_ref)
+
+
 def test_solve_gains_recovers_known_gains(mw, small):
     rng = np.random.default_rng(4)
     M = orc.predict(small.uvw, small.freq, _catalogue(rng, 5))
