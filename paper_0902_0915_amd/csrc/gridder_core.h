@@ -554,9 +554,39 @@ __device__ inline void merge_cell(float2 *grid, const float *partial, const int3
             for (int k = rg.x + 1; k < rg.y; k++)
                 add_cell<NC>(partial + ((int64_t)work_ids[k] * R * R + off[t]) * NC, acc);
         }
+    } else if (2 * h <= T) {
+        // 8 components, at most two covering tiles per axis (the halo is at most half a
+        // tile): the rows tyc + dy0 and tyc + dy0 + 1 and the columns likewise, with the four
+        // first-item loads in flight together, then the same order as below
+        float first[4][NC];
+        int ent[4], off[4];
+        const int dy0 = (y & (T - 1)) < h ? -1 : 0, dx0 = (x & (T - 1)) < h ? -1 : 0;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int tty = tyc + dy0 + (t >> 1), ttx = txc + dx0 + (t & 1);
+            const int r = y - (tty * T - h), c = x - (ttx * T - h);
+            const bool ok = tty >= m.ty_lo && tty < m.ty_lo + m.ntyb && r >= 0 && r < R && ttx >= m.tx_lo &&
+                            ttx < m.tx_lo + m.ntxb && c >= 0 && c < R;
+            ent[t] = ok ? (tty - m.ty_lo) * m.ntxb + (ttx - m.tx_lo) : -1;
+            off[t] = r * R + c;
+            const int f = ok ? fid[ent[t]] : -1;
+#pragma unroll
+            for (int q = 0; q < NC; q++) first[t][q] = 0.0f;
+            if (f >= 0) add_cell<NC>(partial + ((int64_t)f * R * R + off[t]) * NC, first[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            if (ent[t] < 0) continue;
+            const int2 rg = rng[ent[t]];
+            if (rg.y <= rg.x) continue;
+#pragma unroll
+            for (int q = 0; q < NC; q++) acc[q] += first[t][q];
+            for (int k = rg.x + 1; k < rg.y; k++)
+                add_cell<NC>(partial + ((int64_t)work_ids[k] * R * R + off[t]) * NC, acc);
+        }
     } else {
-        // 8 components: the same order, one tile at a time (holding nine tiles' values would
-        // cost more registers than the overlap gains)
+        // 8 components and wider halos: the same order, one tile at a time (holding nine
+        // tiles' values would cost more registers than the overlap gains)
         for (int dy = -1; dy <= 1; dy++) {
             const int tty = tyc + dy;
             if (tty < m.ty_lo || tty >= m.ty_lo + m.ntyb) continue;
