@@ -327,12 +327,15 @@ def test_degrid_without_gains_all_lane_layouts(mw, npol, W, weighted):
     assert np.all(got[~keep] == 0)
 
 
-def test_degrid_gains_and_grad_gains(mw):
+@pytest.mark.parametrize("npol,W", [(2, 7), (4, 7), (4, 5)])
+def test_degrid_gains_and_grad_gains(mw, npol, W):
+    """Gains and the gains' gradient through the degridder: the per-group form (2 pols) and
+    the per-run form (4 pols, supports 5 and 7)."""
     rng = np.random.default_rng(11)
-    wl = synth.mwa_scale(seed=2004, nant=40, nchan=4, ntime=2, npol=2, n=256, nsrc=10)
+    wl = synth.mwa_scale(seed=2004, nant=40, nchan=4, ntime=2, npol=npol, n=256, nsrc=10, W=W)
     wl.weights = rng.uniform(0.5, 1.5, wl.ngroups).astype(np.float32)
     gains = synth.random_gains(wl.nant, rng)
-    G = (rng.standard_normal((2, wl.ny, wl.nx)) + 1j * rng.standard_normal((2, wl.ny, wl.nx)))
+    G = (rng.standard_normal((npol, wl.ny, wl.nx)) + 1j * rng.standard_normal((npol, wl.ny, wl.nx)))
     G = G.astype(np.complex64)
     w64 = wl.weights.astype(np.float64)
     pos, keep, _ = oracle_positions(wl, weights=w64)
