@@ -327,13 +327,17 @@ def test_degrid_without_gains_all_lane_layouts(mw, npol, W, weighted):
     assert np.all(got[~keep] == 0)
 
 
-@pytest.mark.parametrize("npol,W", [(2, 7), (4, 7), (4, 5)])
-def test_degrid_gains_and_grad_gains(mw, npol, W):
+@pytest.mark.parametrize("npol,W,nant", [(2, 7, 0), (4, 7, 0), (4, 5, 0), (4, 7, 9000)])
+def test_degrid_gains_and_grad_gains(mw, npol, W, nant):
     """Gains and the gains' gradient through the degridder: the per-group form (2 pols) and
-    the per-run form (4 pols, supports 5 and 7)."""
+    the per-run form (4 pols, supports 5 and 7). Declaring 9000 antennas (the rows use 40)
+    puts the per-antenna sums in HBM instead of LDS, and builds the plan's calibration lists
+    by the host path for large arrays."""
     rng = np.random.default_rng(11)
     wl = synth.mwa_scale(seed=2004, nant=40, nchan=4, ntime=2, npol=npol, n=256, nsrc=10, W=W)
     wl.weights = rng.uniform(0.5, 1.5, wl.ngroups).astype(np.float32)
+    if nant:
+        wl.nant = nant
     gains = synth.random_gains(wl.nant, rng)
     G = (rng.standard_normal((npol, wl.ny, wl.nx)) + 1j * rng.standard_normal((npol, wl.ny, wl.nx)))
     G = G.astype(np.complex64)
