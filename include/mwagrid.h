@@ -319,6 +319,15 @@ mw_status mw_wstack_combine(mw_plan plan, const void *const *images, void *out, 
 mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out);
 
 /*
+ * Copy instance inst's gridding order to host memory (the sort by uv tile that stands for the
+ * memory structures Section 3.2 says the port needed): order_host uint32 [nkept] = the input
+ * index of each kept group in the order the gridder and degridder take them (tile, then cell,
+ * then row sub-position; equal keys in input order). Synchronous. MW_ERR_INVALID_ARG: inst
+ * out of range or NULL.
+ */
+mw_status mw_plan_order(mw_plan plan, int32_t inst, uint32_t *order_host);
+
+/*
  * Copy instance inst's integer plan outputs to host memory: pos_host int32 [ngroups][4] =
  * cx, cy, px, py for kept groups and -1, -1, -1, -1 for dropped ones. Synchronous.
  */

@@ -503,6 +503,24 @@ mw_status mw_plan_info(mw_plan plan, int32_t inst, mw_plan_stats *out) {
     }
 }
 
+mw_status mw_plan_order(mw_plan plan, int32_t inst, uint32_t *order_host) {
+    try {
+        mwg::Status s = check_plan(plan);
+        if (!s.ok()) return fail(s);
+        mwg::Plan *P = (mwg::Plan *)plan;
+        if (inst < 0 || inst >= (int)P->inst.size() || !order_host)
+            return fail(MW_ERR_INVALID_ARG, "inst out of range or order_host NULL");
+        const mwg::Instance &I = *P->inst[inst];
+        if (I.nkept > 0 && hipMemcpy(order_host, I.perm, 4 * (size_t)I.nkept, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(MW_ERR_HIP, "hipMemcpy of the gridding order failed");
+        return MW_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MW_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(MW_ERR_HIP, "unexpected exception");
+    }
+}
+
 mw_status mw_plan_positions(mw_plan plan, int32_t inst, int32_t *pos_host) {
     try {
         mwg::Status s = check_plan(plan);

@@ -71,6 +71,7 @@ _lib.mw_peel.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _v
 _lib.mw_wstack_combine.argtypes = [_vp, _PP, _vp, _i32, _vp]
 _lib.mw_plan_info.argtypes = [_vp, _i32, ctypes.POINTER(MwPlanStats)]
 _lib.mw_plan_positions.argtypes = [_vp, _i32, _vp]
+_lib.mw_plan_order.argtypes = [_vp, _i32, _vp]
 _lib.mw_plan_tables.argtypes = [_vp, _i32, _vp, _vp, _vp]
 _lib.mw_plan_destroy.argtypes = [_vp]
 _lib.mw_plan_set_timing.argtypes = [_vp, _i32]
@@ -81,7 +82,7 @@ _lib.mw_last_error.restype = ctypes.c_char_p
 _lib.mw_abi_version.argtypes = []
 _lib.mw_abi_version.restype = _i32
 for _f in ("mw_grid_plan", "mw_grid", "mw_degrid", "mw_image", "mw_plan_info",
-           "mw_plan_positions", "mw_plan_tables", "mw_plan_destroy", "mw_plan_set_timing",
+           "mw_plan_positions", "mw_plan_order", "mw_plan_tables", "mw_plan_destroy", "mw_plan_set_timing",
            "mw_plan_kernel_ms", "mw_stokes", "mw_grid_noalloc", "mw_predict", "mw_solve_gains",
            "mw_peel", "mw_wstack_combine"):
     getattr(_lib, _f).restype = _i32
@@ -272,6 +273,12 @@ class Plan:
         ng = np.asarray(sp.uvw).shape[0] * np.asarray(sp.freq).shape[0]
         out = np.empty((ng, 4), dtype=np.int32)
         _check(_lib.mw_plan_positions(self.handle, inst, out.ctypes.data))
+        return out
+
+    def order(self, inst=0):
+        """mw_plan_order: the input index of each kept group in the gridding order."""
+        out = np.empty(self.info(inst)["nkept"], dtype=np.uint32)
+        _check(_lib.mw_plan_order(self.handle, inst, out.ctypes.data))
         return out
 
     def tables(self, inst=0):
