@@ -121,8 +121,8 @@ def percentiles(fn, steps, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding is a design in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "work over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 
