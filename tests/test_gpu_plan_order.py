@@ -27,18 +27,10 @@ def _order(mw, wl, **tuning):
         return plan.order(0), plan.positions(0), info
 
 
-@pytest.mark.parametrize("n,order,tile", [(512, 3, 8), (128, 3, 8), (128, 3, 16), (256, 1, 8), (256, 2, 8)])
-def test_gridding_order(mw, n, order, tile):
-    rng = np.random.default_rng(90 + n + order)
-    wl = synth.mwa_scale(seed=2090, nant=48, nchan=8, ntime=2, npol=1, n=n, nsrc=5, make_vis=False)
-    wl.flags = (rng.random(wl.ngroups) < 0.1).astype(np.uint8)
-    perm, pos, info = _order(mw, wl, variant=4, tile=tile, order=order)
-    assert info["tile"] == tile and info["order"] == order
+def _check_order(wl, perm, pos, info, order, tile):
     keep = pos[:, 0] >= 0
     assert info["nkept"] == int(keep.sum()) == perm.size
     np.testing.assert_array_equal(np.sort(perm), np.flatnonzero(keep))  # a permutation of the kept
-    if order == 3:
-        assert wl.ngroups > n * n or n == 512  # the table path for n = 128
     cx, cy, py = pos[perm, 0], pos[perm, 1], pos[perm, 3]
     ntx = (wl.nx + tile - 1) // tile
     t = (cy // tile) * ntx + cx // tile
@@ -57,3 +49,28 @@ def test_gridding_order(mw, n, order, tile):
     if order == 1:  # cells row by row within a tile
         lr = (cy % tile) * tile + cx % tile
         assert np.all(lr[1:][same_tile] >= lr[:-1][same_tile])
+
+
+@pytest.mark.parametrize("n,order,tile", [(512, 3, 8), (128, 3, 8), (128, 3, 16), (256, 1, 8), (256, 2, 8)])
+def test_gridding_order(mw, n, order, tile):
+    rng = np.random.default_rng(90 + n + order)
+    wl = synth.mwa_scale(seed=2090, nant=48, nchan=8, ntime=2, npol=1, n=n, nsrc=5, make_vis=False)
+    wl.flags = (rng.random(wl.ngroups) < 0.1).astype(np.uint8)
+    if order == 3 and n == 128:
+        assert wl.ngroups > n * n  # more groups than cells: the rank table
+    perm, pos, info = _order(mw, wl, variant=4, tile=tile, order=order)
+    assert info["tile"] == tile and info["order"] == order
+    _check_order(wl, perm, pos, info, order, tile)
+
+
+def test_gridding_order_of_a_batched_plan(mw):
+    """A plan of four instances sorts each on a worker thread, once the batch has chosen its
+    tile: every instance's order has the same properties at that tile."""
+    jobs = [synth.mwa_scale(seed=2091 + k, nant=24 + 8 * k, nchan=4 + 2 * k, ntime=2, npol=1, n=n,
+                            nsrc=3, make_vis=False) for k, n in enumerate((256, 512, 128, 256))]
+    specs = [mw.InstanceSpec.from_workload(j, with_ants=False) for j in jobs]
+    with mw.Plan(specs) as plan:
+        for k, wl in enumerate(jobs):
+            info = plan.info(k)
+            _check_order(wl, plan.order(k), plan.positions(k), info, info["order"], info["tile"])
+
